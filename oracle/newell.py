@@ -1,0 +1,198 @@
+"""Cell-averaged demagnetizing tensor N(r) between two equal cuboid cells.
+
+Paper: Sec. 3, Eq. 4 (the convolution sum over cell-centred positions with
+tensors generalized from the Newell et al. formulas) and Table 1, row
+"Demagnetizing Field" (H(r0) = -sum_r N(r - r0) M(r), N from the Newell
+formulas).  The paper cites the formulas but does not print them; the closed
+forms below are the published Newell f/g functions combined with the 27-point
+second-difference stencil.  N(r) is the average over the target cell of the
+field produced by a uniformly magnetized source cell per unit magnetization,
+with the sign convention H = -N M.
+
+Numerics (the paper is silent; the reading is recorded with the design notes):
+  * |r| < 3 h_max : Newell closed form in FP64.  Its 27-term stencil cancels
+    catastrophically, losing roughly eps * (|r|/h)^6, which stays <= 1e-11
+    relative inside this radius.
+  * |r| >= 3 h_max: the definition itself, N(r) = 1/(4 pi V) * integral over
+    u in [-h, h]^3 of prod_i (h_i - |u_i|) * D(r + u), with the point-dipole
+    kernel D(v) = (|v|^2 I - 3 v v^T)/|v|^5, integrated by Gauss-Legendre
+    quadrature on each half-axis [0, h_i] (the tent weight is smooth there):
+    8 nodes per half-axis below 6 h_max, 6 below 16 h_max, 4 below 40 h_max,
+    3 beyond.  Measured against 60-digit evaluations this is <= 1e-11.
+
+Component order everywhere: xx, yy, zz, xy, xz, yz.
+"""
+import math
+import numpy as np
+
+COMPONENTS = ("xx", "yy", "zz", "xy", "xz", "yz")
+
+# Parity of each component under r_a -> -r_a for a = x, y, z (+1 even, -1 odd).
+PARITY = {
+    "xx": (1, 1, 1), "yy": (1, 1, 1), "zz": (1, 1, 1),
+    "xy": (-1, -1, 1), "xz": (-1, 1, -1), "yz": (1, -1, -1),
+}
+
+NEAR_RADIUS = 3.0            # in units of the largest cell edge
+GL_BANDS = ((6.0, 8), (16.0, 6), (40.0, 4), (math.inf, 3))
+
+
+def _safe_div(num, den):
+    out = np.zeros(np.broadcast(num, den).shape)
+    nz = den != 0
+    np.divide(num, den, out=out, where=nz)
+    return out
+
+
+def newell_f(x, y, z):
+    """Newell's f(x, y, z) for the diagonal component (vectorized, FP64).
+
+    Terms whose prefactor vanishes are taken as their limit, 0."""
+    x, y, z = (np.asarray(a, dtype=np.float64) for a in (x, y, z))
+    x2, y2, z2 = x * x, y * y, z * z
+    R = np.sqrt(x2 + y2 + z2)
+    out = (2.0 * x2 - y2 - z2) * R / 6.0
+    rxz = np.sqrt(x2 + z2)
+    rxy = np.sqrt(x2 + y2)
+    out = out + np.where(rxz > 0, 0.5 * y * (z2 - x2) * np.arcsinh(_safe_div(y, rxz)), 0.0)
+    out = out + np.where(rxy > 0, 0.5 * z * (y2 - x2) * np.arcsinh(_safe_div(z, rxy)), 0.0)
+    out = out - np.where(x != 0, x * y * z * np.arctan(_safe_div(y * z, x * R)), 0.0)
+    return out
+
+
+def newell_g(x, y, z):
+    """Newell's g(x, y, z) for the off-diagonal component (vectorized, FP64)."""
+    x, y, z = (np.asarray(a, dtype=np.float64) for a in (x, y, z))
+    x2, y2, z2 = x * x, y * y, z * z
+    R = np.sqrt(x2 + y2 + z2)
+    rxy = np.sqrt(x2 + y2)
+    ryz = np.sqrt(y2 + z2)
+    rxz = np.sqrt(x2 + z2)
+    out = -x * y * R / 3.0
+    out = out + np.where(rxy > 0, x * y * z * np.arcsinh(_safe_div(z, rxy)), 0.0)
+    out = out + np.where(ryz > 0, y / 6.0 * (3.0 * z2 - y2) * np.arcsinh(_safe_div(x, ryz)), 0.0)
+    out = out + np.where(rxz > 0, x / 6.0 * (3.0 * z2 - x2) * np.arcsinh(_safe_div(y, rxz)), 0.0)
+    out = out - np.where(z != 0, z * z2 / 6.0 * np.arctan(_safe_div(x * y, z * R)), 0.0)
+    out = out - np.where(y != 0, z * y2 / 2.0 * np.arctan(_safe_div(x * z, y * R)), 0.0)
+    out = out - np.where(x != 0, z * x2 / 2.0 * np.arctan(_safe_div(y * z, x * R)), 0.0)
+    return out
+
+
+def _stencil(phi, X, Y, Z, a, b, c):
+    """Second difference of phi over the 27 points (X + i a, Y + j b, Z + k c),
+    i, j, k in {-1, 0, 1}, weights w_0 = 2, w_{+-1} = -1, divided by 4 pi a b c."""
+    w = {-1: -1.0, 0: 2.0, 1: -1.0}
+    acc = np.zeros(np.broadcast(X, Y, Z).shape)
+    for i in (-1, 0, 1):
+        for j in (-1, 0, 1):
+            for k in (-1, 0, 1):
+                acc = acc + w[i] * w[j] * w[k] * phi(X + i * a, Y + j * b, Z + k * c)
+    return acc / (4.0 * math.pi * a * b * c)
+
+
+def newell_near(X, Y, Z, h):
+    """All six components by the Newell closed form; returns an array [6, ...].
+
+    Each component is f or g with the axes permuted so that the first argument
+    is the first tensor index: yy swaps x<->y, zz swaps x<->z, xz swaps y<->z,
+    yz maps (x, y, z) -> (y, z, x)."""
+    dx, dy, dz = h
+    return np.stack([
+        _stencil(newell_f, X, Y, Z, dx, dy, dz),   # xx
+        _stencil(newell_f, Y, X, Z, dy, dx, dz),   # yy
+        _stencil(newell_f, Z, Y, X, dz, dy, dx),   # zz
+        _stencil(newell_g, X, Y, Z, dx, dy, dz),   # xy
+        _stencil(newell_g, X, Z, Y, dx, dz, dy),   # xz
+        _stencil(newell_g, Y, Z, X, dy, dz, dx),   # yz
+    ])
+
+
+def _tent_nodes(hi, n):
+    """Nodes and weights of int_{-h}^{h} (h - |u|) F(u) du by n-point
+    Gauss-Legendre on each half-axis."""
+    t, w = np.polynomial.legendre.leggauss(n)
+    u = 0.5 * hi * (1.0 + t)
+    wt = 0.5 * hi * w * (hi - u)
+    return np.concatenate([u, -u]), np.concatenate([wt, wt])
+
+
+def gl_far(X, Y, Z, h, n):
+    """All six components from the defining integral of the dipole kernel
+    against the tent weight, with n Gauss-Legendre nodes per half-axis.
+    Valid (accurate) only away from the source cell; returns [6, ...]."""
+    X, Y, Z = (np.asarray(a, dtype=np.float64) for a in (X, Y, Z))
+    shape = np.broadcast(X, Y, Z).shape
+    acc = np.zeros((6,) + shape)
+    ux, wx = _tent_nodes(h[0], n)
+    uy, wy = _tent_nodes(h[1], n)
+    uz, wz = _tent_nodes(h[2], n)
+    for a in range(len(ux)):
+        vx = X + ux[a]
+        for b in range(len(uy)):
+            vy = Y + uy[b]
+            for c in range(len(uz)):
+                vz = Z + uz[c]
+                r2 = vx * vx + vy * vy + vz * vz
+                inv5 = 1.0 / (r2 * r2 * np.sqrt(r2))
+                wgt = wx[a] * wy[b] * wz[c] * inv5
+                acc[0] += wgt * (r2 - 3.0 * vx * vx)
+                acc[1] += wgt * (r2 - 3.0 * vy * vy)
+                acc[2] += wgt * (r2 - 3.0 * vz * vz)
+                acc[3] += wgt * (-3.0 * vx * vy)
+                acc[4] += wgt * (-3.0 * vx * vz)
+                acc[5] += wgt * (-3.0 * vy * vz)
+    return acc / (4.0 * math.pi * h[0] * h[1] * h[2])
+
+
+def tensor_at(X, Y, Z, h):
+    """N(r) at offsets r = (X, Y, Z) (metres, any sign), choosing the closed
+    form near the source and the quadrature far from it.  Returns [6, ...]."""
+    X, Y, Z = np.broadcast_arrays(*(np.asarray(a, dtype=np.float64) for a in (X, Y, Z)))
+    hmax = max(h)
+    dist = np.sqrt(X * X + Y * Y + Z * Z) / hmax
+    out = np.zeros((6,) + X.shape)
+    near = dist < NEAR_RADIUS
+    if near.any():
+        out[:, near] = newell_near(X[near], Y[near], Z[near], h)
+    lo = NEAR_RADIUS
+    for hi, nodes in GL_BANDS:
+        sel = (dist >= lo) & (dist < hi)
+        if sel.any():
+            out[:, sel] = gl_far(X[sel], Y[sel], Z[sel], h, nodes)
+        lo = hi
+    return out
+
+
+def tensor_octant(n, h):
+    """N at the non-negative lattice offsets (i dx, j dy, k dz), 0 <= i < nx,
+    0 <= j < ny, 0 <= k < nz.  Returns [6, nz, ny, nx] (x fastest)."""
+    nx, ny, nz = n
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return tensor_at(i * h[0], j * h[1], k * h[2], h)
+
+
+def tensor_full(n, h):
+    """N at every lattice offset -(n_a - 1) .. (n_a - 1), built from the octant
+    by the parity of each component.  Returns [6, 2nz-1, 2ny-1, 2nx-1] with the
+    zero offset at index (nz-1, ny-1, nx-1)."""
+    nx, ny, nz = n
+    octn = tensor_octant(n, h)
+    full = np.zeros((6, 2 * nz - 1, 2 * ny - 1, 2 * nx - 1))
+    sx = np.abs(np.arange(-(nx - 1), nx))
+    sy = np.abs(np.arange(-(ny - 1), ny))
+    sz = np.abs(np.arange(-(nz - 1), nz))
+    negx = np.arange(-(nx - 1), nx) < 0
+    negy = np.arange(-(ny - 1), ny) < 0
+    negz = np.arange(-(nz - 1), nz) < 0
+    for c, name in enumerate(COMPONENTS):
+        px, py, pz = PARITY[name]
+        vals = octn[c][np.ix_(sz, sy, sx)]
+        sign = np.ones(vals.shape)
+        if px < 0:
+            sign = sign * np.where(negx, -1.0, 1.0)[None, None, :]
+        if py < 0:
+            sign = sign * np.where(negy, -1.0, 1.0)[None, :, None]
+        if pz < 0:
+            sign = sign * np.where(negz, -1.0, 1.0)[:, None, None]
+        full[c] = vals * sign
+    return full
