@@ -19,7 +19,8 @@ import scipy.fft
 from .newell import tensor_full
 
 MU0 = 4.0e-7 * math.pi
-_WORKERS = os.cpu_count() or 1
+# FFT threads: the CPUs this process may use, at most 16
+_WORKERS = max(1, min(16, len(os.sched_getaffinity(0))))
 
 
 def padded_len(n):
@@ -59,6 +60,38 @@ def direct_sum(M, h, Nfull=None):
                     H[a] -= (N[a][0][win] * m[0] + N[a][1][win] * m[1]
                              + N[a][2][win] * m[2])
     return H
+
+
+def direct_sum_at(M, h, targets, Noct):
+    """H at the listed target cells (tz, ty, tx) by the direct sum over every
+    source, H_t = -sum_s N(r_t - r_s) M_s, with N looked up in the octant
+    Noct [6, nz, ny, nx] and reflected by each component's parity.
+    Returns [len(targets), 3]."""
+    from .newell import COMPONENTS, PARITY
+    M = np.asarray(M, dtype=np.float64)
+    _, nz, ny, nx = M.shape
+    out = np.zeros((len(targets), 3))
+    for q, (tz, ty, tx) in enumerate(targets):
+        oz = tz - np.arange(nz)
+        oy = ty - np.arange(ny)
+        ox = tx - np.arange(nx)
+        az, ay, ax = np.abs(oz), np.abs(oy), np.abs(ox)
+        sgn = [np.where(o < 0, -1.0, 1.0) for o in (ox, oy, oz)]
+        N = []
+        for c, name in enumerate(COMPONENTS):
+            v = Noct[c][np.ix_(az, ay, ax)]
+            px, py, pz = PARITY[name]
+            if px < 0:
+                v = v * sgn[0][None, None, :]
+            if py < 0:
+                v = v * sgn[1][None, :, None]
+            if pz < 0:
+                v = v * sgn[2][:, None, None]
+            N.append(v)
+        Nm = _as_matrix(N)
+        for a in range(3):
+            out[q, a] = -float(np.sum(Nm[a][0] * M[0] + Nm[a][1] * M[1] + Nm[a][2] * M[2]))
+    return out
 
 
 def kernel_grid(n, h, Nfull=None):

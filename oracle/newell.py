@@ -144,10 +144,21 @@ def gl_far(X, Y, Z, h, n):
     return acc / (4.0 * math.pi * h[0] * h[1] * h[2])
 
 
+_CHUNK = 1 << 15
+
+
 def tensor_at(X, Y, Z, h):
     """N(r) at offsets r = (X, Y, Z) (metres, any sign), choosing the closed
     form near the source and the quadrature far from it.  Returns [6, ...]."""
     X, Y, Z = np.broadcast_arrays(*(np.asarray(a, dtype=np.float64) for a in (X, Y, Z)))
+    if X.size > _CHUNK:
+        # evaluate in slices that stay cache resident; same arithmetic
+        flat = [a.reshape(-1) for a in (X, Y, Z)]
+        out = np.empty((6, X.size))
+        for s0 in range(0, X.size, _CHUNK):
+            sl = slice(s0, s0 + _CHUNK)
+            out[:, sl] = tensor_at(flat[0][sl], flat[1][sl], flat[2][sl], h)
+        return out.reshape((6,) + X.shape)
     hmax = max(h)
     dist = np.sqrt(X * X + Y * Y + Z * Z) / hmax
     out = np.zeros((6,) + X.shape)

@@ -144,3 +144,14 @@ def test_translation_invariance():
     Hb2 = conv.fft_conv(big2, h)
     assert np.allclose(Hb[:, 1:3, 2:5, 3:7], Hs, rtol=0, atol=1e-13)
     assert np.allclose(Hb2[:, 2:4, 3:6, 5:9], Hs, rtol=0, atol=1e-13)
+
+
+def test_sampled_direct_sum_matches_full_direct_sum():
+    from oracle.newell import tensor_octant
+    n, h = (9, 6, 4), (2e-9, 3e-9, 1e-9)
+    M = inputs.unit_sphere(n, seed=12).astype(np.float64)
+    Hd = conv.direct_sum(M, h)
+    targets = [(0, 0, 0), (3, 5, 8), (1, 2, 4), (2, 0, 7)]
+    Hs = conv.direct_sum_at(M, h, targets, tensor_octant(n, h))
+    for q, (tz, ty, tx) in enumerate(targets):
+        assert np.allclose(Hs[q], Hd[:, tz, ty, tx], rtol=1e-13, atol=0)
