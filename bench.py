@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark of the demagnetizing-field hot path on one MI355X.
+
+One step = the whole path on one batch: the field H_d = -N * (Ms m) with the
+demag energy (forward), then the gradient of <G, H_d> with respect to m
+(backward, the same convolution applied to G).  Workload: a 512x512x16 mesh of
+2x2x1 nm cells, Ms = 1.1e6 A/m, random-domain magnetization (Voronoi grains of
+~50 cells, seed 10) and a Gaussian upstream gradient (seed 110), open
+boundaries, FP32.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  Per-pass durations come from HIP events recorded by the
+library between its passes inside the timed region; the middle pass (y FFT,
+kernel product, inverse y FFT) moves the most bytes and is the one reported
+against the HBM roofline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "512x512x16": dict(n=(512, 512, 16), h=(2e-9, 2e-9, 1e-9), Ms=1.1e6, seed=10),
+    "1024x1024x4": dict(n=(1024, 1024, 4), h=(2e-9, 2e-9, 1e-9), Ms=1.1e6, seed=11),
+    "256x256x8": dict(n=(256, 256, 8), h=(4e-9, 4e-9, 4e-9), Ms=8e5, seed=2),
+    "256x128x4": dict(n=(256, 128, 4), h=(5e-9, 5e-9, 2e-9), Ms=8e5, seed=4),
+}
+
+
+def mid_pass_bytes(n):
+    """Algorithmic HBM bytes of one middle-pass launch: read and write the
+    x/z-transformed spectrum of the three components (3 * Nz * (Nx/2+1) * ny
+    complex FP32) and read the kernel-spectrum octant once (6 * (Nz/2+1) *
+    (Ny/2+1) * (Nx/2+1) FP32)."""
+    from oracle.conv import padded_len  # plain arithmetic on sizes
+    nx, ny, nz = n
+    Nx, Ny, Nz = padded_len(nx), padded_len(ny), padded_len(nz)
+    Kx = Nx // 2 + 1 if Nx > 1 else 1
+    Ky = Ny // 2 + 1 if Ny > 1 else 1
+    Kz = Nz // 2 + 1 if Nz > 1 else 1
+    spec = 3 * Nz * Kx * ny * 8
+    return 2 * spec + 6 * Kz * Ky * Kx * 4
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="512x512x16", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2008_02478_amd import inputs, lib
+    from paper_2008_02478_amd.demag import DemagPlan
+    if not os.path.exists(lib.LIB_PATH):
+        from paper_2008_02478_amd import build_lib
+        build_lib.build()
+
+    wl = WORKLOADS[args.workload]
+    n, h, Ms = wl["n"], wl["h"], wl["Ms"]
+    ncell = n[0] * n[1] * n[2]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.workload in ("512x512x16", "1024x1024x4"):
+        m_np = inputs.voronoi(n, (h[0] * 1e9, h[1] * 1e9, h[2] * 1e9), seed=wl["seed"])
+    else:
+        m_np = inputs.unit_sphere(n, seed=wl["seed"])
+    G_np = inputs.gaussian(n, seed=wl["seed"] + 100)
+    t0 = time.time()
+    plan = DemagPlan(n, h, device=dev)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    m = torch.from_numpy(m_np).to(dev)
+    G = torch.from_numpy(G_np).to(dev)
+    H = torch.empty_like(m)
+    grad = torch.empty_like(m)
+    E = torch.empty((), dtype=torch.float64, device=dev)
+
+    import ctypes
+    L = lib.load()
+
+    def step():
+        plan.field(m, Ms, out=H, energy=False)
+        plan.backward(G, Ms, out=grad)
+
+    # field with energy: done through the C ABI so the energy lands in E
+    def step_energy():
+        lib.check(L.demag_field(plan._p, ctypes.c_void_p(m.data_ptr()), None, Ms, ctypes.c_void_p(H.data_ptr()), 0,
+                                ctypes.c_void_p(E.data_ptr()),
+                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        plan.backward(G, Ms, out=grad)
+
+    for _ in range(args.warmup):
+        step_energy()
+    torch.cuda.synchronize()
+
+    # per-pass events: 4 per call, 2 calls per step
+    K = args.steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(2 * K)]
+    for s in evs:
+        for e in s:
+            e.record()
+    torch.cuda.synchronize()
+    handles = [(ctypes.c_void_p * 4)(*[e.cuda_event for e in s]) for s in evs]
+
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for k in range(K):
+        lib.check(L.demag_set_timing_events(plan._p, handles[2 * k], 4))
+        lib.check(L.demag_field(plan._p, ctypes.c_void_p(m.data_ptr()), None, Ms, ctypes.c_void_p(H.data_ptr()), 0,
+                                ctypes.c_void_p(E.data_ptr()),
+                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        lib.check(L.demag_set_timing_events(plan._p, handles[2 * k + 1], 4))
+        plan.backward(G, Ms, out=grad)
+    stop.record()
+    torch.cuda.synchronize()
+    lib.check(L.demag_set_timing_events(plan._p, None, 0))
+    ms_step = start.elapsed_time(stop) / K
+
+    passes = {"fwd_xz": [], "mid_y": [], "inv_zx": []}
+    for s in evs:
+        passes["fwd_xz"].append(s[0].elapsed_time(s[1]))
+        passes["mid_y"].append(s[1].elapsed_time(s[2]))
+        passes["inv_zx"].append(s[2].elapsed_time(s[3]))
+    pass_us = {k: 1e3 * float(np.mean(v)) for k, v in passes.items()}
+    mid_bytes = mid_pass_bytes(n)
+    achieved = mid_bytes / (pass_us["mid_y"] * 1e-6) / 1e9
+
+    out = {
+        "metric": "demag field evals/sec and cell-updates/s (fwd+bwd) at 512x512x16 FP32; HBM GB/s",
+        "value": ncell / (ms_step * 1e-3),
+        "unit": "cell-updates/s (fwd+bwd)",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{n[0]}x{n[1]}x{n[2]} mesh of {h[0]*1e9:g}x{h[1]*1e9:g}x{h[2]*1e9:g} nm cells, "
+                        f"Ms={Ms:g} A/m, open boundaries; step = field+energy forward and <G,H> backward",
+            "mesh": list(n), "cell_m": list(h),
+        },
+        "evals_per_s_fwd_bwd_pairs": 1e3 / ms_step,
+        "pass_us": pass_us,
+        "setup_s": setup_s,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_mid (y FFT + kernel product + inverse y FFT)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "algorithmic_bytes_per_launch": mid_bytes,
+        },
+    }
+
+    if not args.no_cpu_baseline:
+        from oracle import conv
+        from oracle.newell import tensor_full
+        t0 = time.time()
+        Nfull = tensor_full(n, h)
+        tensor_s = time.time() - t0
+        M = Ms * m_np.astype(np.float64)
+        t0 = time.time()
+        Hr = conv.fft_conv(M, h, Nfull)
+        gr = Ms * conv.fft_conv(G_np.astype(np.float64), h, Nfull)
+        cpu_s = time.time() - t0
+        Hg = H.cpu().numpy().astype(np.float64)
+        gg = grad.cpu().numpy().astype(np.float64)
+        out["cpu_baseline"] = {
+            "value": ncell / cpu_s,
+            "unit": "cell-updates/s (fwd+bwd)",
+            "cores": conv._WORKERS,
+            "kind": "oracle",
+            "sample": "one forward + backward step of the same workload by the FP64 oracle's FFT convolution "
+                      f"(tensor set-up excluded, {tensor_s:.1f} s)",
+            "seconds": cpu_s,
+        }
+        out["accuracy"] = {
+            "H_rel_l2_vs_fp64_oracle": float(np.linalg.norm(Hg - Hr) / np.linalg.norm(Hr)),
+            "grad_rel_l2_vs_fp64_oracle": float(np.linalg.norm(gg - gr) / np.linalg.norm(gr)),
+            "E_rel_vs_fp64_oracle": abs(float(E) - conv.energy(M, Hr, h)) / abs(conv.energy(M, Hr, h)),
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

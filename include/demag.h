@@ -1,0 +1,121 @@
+/*
+ * demag.h - C ABI of the MI355X demagnetizing-field library.
+ *
+ * Computes H_d = -N * M on a regular finite-difference mesh: the
+ * demagnetizing-field term of Table 1 (H(r0) = -sum_r N(r - r0) M(r), N the
+ * cell-averaged Newell tensor) and the single-mesh form of Sec. 3, Eq. 4,
+ * evaluated with the convolution theorem on a zero-padded grid (Sec. 7: 1D
+ * transforms along x, y and z, point-wise product with the transformed
+ * kernel, inverse transforms; the z transform, product and inverse z
+ * transform fused into one pass, the paper's pipelined convolution).  The
+ * energy follows from the field/energy relation of Appendix A,
+ * E = -(mu0/2) V sum_cells M . H.
+ *
+ * Conventions
+ *  - Every function returns DEMAG_OK (0) or a negative status; no other error
+ *    channel crosses the ABI.  demag_last_error() gives a message for the
+ *    calling thread's last failure.
+ *  - Arguments and sizes are checked on the host before any HIP call.
+ *  - Device pointers are allocated and owned by the caller; the library never
+ *    frees them.  `stream` is a hipStream_t (NULL = the default stream).
+ *  - demag_field, demag_energy and demag_backward only enqueue work on
+ *    `stream`: they neither allocate nor synchronize.  Calls that share a
+ *    plan share its work buffer and must be ordered on one stream.
+ *  - Arrays of vectors are SoA [3][nz][ny][nx], x fastest, FP32.  Lengths in
+ *    metres, M and H in A/m, energies in joules (FP64).
+ *  - Supported sizes: 1 <= nx <= 2048, 1 <= ny <= 1024, 1 <= nz <= 16, open
+ *    boundaries (each axis zero-padded to the next power of two >= 2n-1).
+ *    Periodic boundaries are reserved flags and return DEMAG_EUNSUPPORTED.
+ */
+#ifndef DEMAG_H
+#define DEMAG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct demag_plan demag_plan;
+
+enum {
+  DEMAG_OK = 0,
+  DEMAG_EINVAL = -1,        /* invalid argument (null pointer, bad size, NaN cell) */
+  DEMAG_EUNSUPPORTED = -2,  /* valid but not supported (size limits, periodic axes) */
+  DEMAG_ENOMEM = -3,        /* host or set-up device allocation failed */
+  DEMAG_EHIP = -4,          /* a HIP runtime call failed */
+  DEMAG_ESTATE = -5         /* wrong call order (field before bind, bind twice) */
+};
+
+enum { DEMAG_PBC_X = 1, DEMAG_PBC_Y = 2, DEMAG_PBC_Z = 4 };
+enum { DEMAG_ACCUMULATE = 1 };   /* H += H_d instead of H = H_d */
+
+/* Validate a mesh of nx*ny*nz cells of size dx*dy*dz metres and create a plan
+ * (host memory only, no HIP call).  pbc_flags: OR of DEMAG_PBC_*; any periodic
+ * axis currently returns DEMAG_EUNSUPPORTED.  pbc_images is ignored for open
+ * boundaries.  On success *out owns the plan (free with demag_destroy). */
+int demag_setup(demag_plan** out, int nx, int ny, int nz, double dx, double dy, double dz,
+                unsigned pbc_flags, int pbc_images);
+
+/* Padded FFT lengths of the plan (powers of two >= 2n-1, or 1). */
+int demag_padded_dims(const demag_plan* plan, int* Nx, int* Ny, int* Nz);
+
+/* Bytes of the two device buffers the caller provides to demag_bind:
+ * kernel_bytes - twiddle table and the FP32 kernel spectrum (read-only after
+ *                bind);
+ * work_bytes   - the padded spectrum of M and energy partials (scratch that
+ *                every field call overwrites). */
+int demag_buffer_bytes(const demag_plan* plan, size_t* kernel_bytes, size_t* work_bytes);
+
+/* Attach the caller's buffers (256-byte aligned device memory on the current
+ * device) and build the kernel spectrum on `stream`: the Newell tensor in FP64
+ * (Sec. 3 Eq. 4; Table 1), its transform on the padded grid in FP64, stored in
+ * FP32 with the factor -1/(Nx Ny Nz).  Set-up only: allocates FP64
+ * temporaries, synchronizes `stream` and frees them before returning.  A plan
+ * binds once (DEMAG_ESTATE otherwise). */
+int demag_bind(demag_plan* plan, void* d_kernel, void* d_work, void* stream);
+
+/* H_d = -N * M with M = Ms * m (Table 1, demagnetizing field).  d_m: unit
+ * magnetization [3][nz][ny][nx]; d_Ms: per-cell saturation magnetization
+ * [nz][ny][nx] or NULL to use the scalar Ms; d_H: output [3][nz][ny][nx]
+ * (overwritten, or incremented with DEMAG_ACCUMULATE).  d_energy: NULL or a
+ * device double that receives E = -(mu0/2) V sum M . H_d, evaluated in the
+ * transform domain (Parseval) without extra memory traffic.  d_m and d_H must
+ * not overlap. */
+int demag_field(const demag_plan* plan, const float* d_m, const float* d_Ms, float Ms, float* d_H,
+                unsigned flags, double* d_energy, void* stream);
+
+/* E = -(mu0/2) V sum_cells Ms m . H for a given field H (any H, e.g. an
+ * accumulated effective field), written to the device double d_energy. */
+int demag_energy(const demag_plan* plan, const float* d_m, const float* d_Ms, float Ms, const float* d_H,
+                 double* d_energy, void* stream);
+
+/* Gradient of L(m) = <G, H_d(m)> + gE * E_demag(m) with respect to m, where
+ * H_d(m) = -N * (Ms m).  N is symmetric and even in r, so the operator is
+ * self-adjoint and d<G,H>/dM = -N * G; with dE/dM = -mu0 V H_d:
+ *   grad_m = Ms * ( -N * G  - mu0 V gE H_d ).
+ * d_G: upstream gradient [3][nz][ny][nx]; d_H: the forward field H_d (read
+ * only when d_gE is not NULL); d_gE: NULL or a device double holding gE;
+ * d_grad_m: output (overwritten, or incremented with DEMAG_ACCUMULATE).
+ * d_G may alias neither d_H nor d_grad_m. */
+int demag_backward(const demag_plan* plan, const float* d_G, const float* d_Ms, float Ms, const float* d_H,
+                   const double* d_gE, float* d_grad_m, unsigned flags, void* stream);
+
+/* Per-pass timing: `events` points to 4 hipEvent_t created by the caller; each
+ * later demag_field / demag_backward call on this plan records them on its
+ * stream before the forward pass, after the forward pass, after the middle
+ * pass and after the inverse pass (the optional energy reduction follows).
+ * NULL (or count 0) turns recording off.  Host-only bookkeeping. */
+int demag_set_timing_events(demag_plan* plan, void* const* events, int count);
+
+/* Free a plan (host memory only).  NULL is accepted. */
+int demag_destroy(demag_plan* plan);
+
+/* Message for the calling thread's last non-OK return ("" if none). */
+const char* demag_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEMAG_H */

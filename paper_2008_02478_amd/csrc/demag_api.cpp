@@ -1,0 +1,363 @@
+// C ABI of the demagnetizing-field library: argument checks, plan geometry,
+// kernel-spectrum set-up and the launch sequence of one field evaluation.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/demag.h"
+#include "fft_core.hpp"
+#include "launch.hpp"
+#include "plan.hpp"
+
+using namespace demag;
+
+struct demag_plan {
+  Geom g;
+  bool bound = false;
+  int device = -1;
+  float2* tw = nullptr;    // twiddle table (start of the kernel buffer)
+  float* K = nullptr;      // kernel spectrum
+  float2* T = nullptr;     // spectrum work buffer
+  double* epart = nullptr; // energy partials
+  size_t kernel_bytes = 0, work_bytes = 0;
+  size_t tw_bytes = 0, spec_bytes = 0, part_count = 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool timing = false;
+};
+
+namespace {
+
+thread_local std::string g_err;
+constexpr double MU0 = 4.0e-7 * M_PI;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return DEMAG_EHIP;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+int padded(int n) {
+  if (n == 1) return 1;
+  int p = 1;
+  while (p < 2 * n - 1) p *= 2;
+  return p;
+}
+
+int ilog2i(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+int line_threads(int M) {  // lanes per line of the x passes (matches LineShape)
+  const int R = M >= 1024 ? 16 : (M >= 8 ? 8 : M);
+  return M / R;
+}
+
+// Gauss-Legendre rule of order n on [-1, 1] by Newton iteration on P_n.
+void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+const char* demag_last_error(void) { return g_err.c_str(); }
+
+int demag_setup(demag_plan** out, int nx, int ny, int nz, double dx, double dy, double dz, unsigned pbc_flags,
+                int pbc_images) {
+  (void)pbc_images;
+  if (!out) return fail(DEMAG_EINVAL, "demag_setup: out is NULL");
+  *out = nullptr;
+  if (nx < 1 || ny < 1 || nz < 1) return fail(DEMAG_EINVAL, "demag_setup: mesh dimensions must be >= 1");
+  if (!(std::isfinite(dx) && std::isfinite(dy) && std::isfinite(dz)) || dx <= 0 || dy <= 0 || dz <= 0)
+    return fail(DEMAG_EINVAL, "demag_setup: cell sizes must be finite and > 0");
+  if (pbc_flags & ~7u) return fail(DEMAG_EINVAL, "demag_setup: unknown boundary flags");
+  if (pbc_flags) return fail(DEMAG_EUNSUPPORTED, "demag_setup: periodic boundaries are not supported");
+  if (nx > 2048 || ny > 1024 || nz > 16)
+    return fail(DEMAG_EUNSUPPORTED, "demag_setup: supported sizes are nx <= 2048, ny <= 1024, nz <= 16");
+  Geom g{};
+  g.nx = nx; g.ny = ny; g.nz = nz;
+  g.Nx = padded(nx); g.Ny = padded(ny); g.Nz = padded(nz);
+  g.lnx = ilog2i(g.Nx); g.lny = ilog2i(g.Ny); g.lnz = ilog2i(g.Nz);
+  g.Kx = g.Nx > 1 ? g.Nx / 2 + 1 : 1;
+  g.Kyh = g.Ny > 1 ? g.Ny / 2 + 1 : 1;
+  g.Kzh = g.Nz > 1 ? g.Nz / 2 + 1 : 1;
+  g.nTiles = (g.Kx + TILE - 1) / TILE;
+  g.dx = dx; g.dy = dy; g.dz = dz;
+  const size_t pitch_bytes = (size_t)((g.Nx >= 4 ? g.Nx / 2 : 1) + 1) * sizeof(float2);
+  if ((size_t)nz * pitch_bytes > 160 * 1024)
+    return fail(DEMAG_EUNSUPPORTED, "demag_setup: nz * (Nx/2 + 1) * 8 bytes must fit in 160 KiB of LDS");
+  // y rows per workgroup of the x passes: enough rows for one round of the
+  // workgroup, within 64 KiB of LDS
+  const int P = g.Nx >= 4 ? g.Nx / 4 : 1;
+  const int rpr = FWD_THREADS / (2 * line_threads(P));
+  int yg = (rpr + nz - 1) / nz;
+  while (yg > 1 && (size_t)yg * nz * pitch_bytes > 65536) --yg;
+  if (yg > ny) yg = ny;
+  if (yg < 1) yg = 1;
+  g.yg = yg;
+
+  demag_plan* p = new (std::nothrow) demag_plan;
+  if (!p) return fail(DEMAG_ENOMEM, "demag_setup: out of host memory");
+  p->g = g;
+  p->tw_bytes = align256((size_t)TW_SIZE * sizeof(float2));
+  p->spec_bytes = align256((size_t)6 * g.Kzh * g.Kyh * g.Kx * sizeof(float));
+  p->kernel_bytes = p->tw_bytes + p->spec_bytes;
+  const size_t ncell = (size_t)nx * ny * nz;
+  p->part_count = (size_t)mid_blocks(g);
+  const size_t ecb = (size_t)energy_cell_blocks(ncell);
+  if (ecb > p->part_count) p->part_count = ecb;
+  p->work_bytes = align256(spectrum_elems(g) * sizeof(float2)) + align256(p->part_count * sizeof(double));
+  *out = p;
+  return DEMAG_OK;
+}
+
+int demag_padded_dims(const demag_plan* p, int* Nx, int* Ny, int* Nz) {
+  if (!p || !Nx || !Ny || !Nz) return fail(DEMAG_EINVAL, "demag_padded_dims: NULL argument");
+  *Nx = p->g.Nx; *Ny = p->g.Ny; *Nz = p->g.Nz;
+  return DEMAG_OK;
+}
+
+int demag_buffer_bytes(const demag_plan* p, size_t* kernel_bytes, size_t* work_bytes) {
+  if (!p || !kernel_bytes || !work_bytes) return fail(DEMAG_EINVAL, "demag_buffer_bytes: NULL argument");
+  *kernel_bytes = p->kernel_bytes;
+  *work_bytes = p->work_bytes;
+  return DEMAG_OK;
+}
+
+int demag_bind(demag_plan* p, void* d_kernel, void* d_work, void* stream) {
+  if (!p) return fail(DEMAG_EINVAL, "demag_bind: plan is NULL");
+  if (p->bound) return fail(DEMAG_ESTATE, "demag_bind: plan is already bound");
+  if (!d_kernel || !d_work) return fail(DEMAG_EINVAL, "demag_bind: NULL buffer");
+  if (!aligned(d_kernel) || !aligned(d_work)) return fail(DEMAG_EINVAL, "demag_bind: buffers must be 256-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Geom& g = p->g;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+
+  // twiddles W_4096^k in FP64, rounded once to FP32
+  std::vector<float2> tw(TW_SIZE);
+  for (int k = 0; k < TW_SIZE; ++k) {
+    const double ang = -2.0 * M_PI * k / TW_SIZE;
+    tw[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+  float2* d_tw = static_cast<float2*>(d_kernel);
+  float* d_K = reinterpret_cast<float*>(static_cast<char*>(d_kernel) + p->tw_bytes);
+
+  // FP64 cos/sin tables per axis
+  const int Ns[3] = {g.Nx, g.Ny, g.Nz};
+  int Nmax = 1;
+  for (int a = 0; a < 3; ++a) Nmax = Ns[a] > Nmax ? Ns[a] : Nmax;
+  std::vector<double> trig((size_t)6 * Nmax);
+  for (int a = 0; a < 3; ++a)
+    for (int m = 0; m < Ns[a]; ++m) {
+      const double ang = 2.0 * M_PI * m / Ns[a];
+      trig[(size_t)(2 * a) * Nmax + m] = std::cos(ang);
+      trig[(size_t)(2 * a + 1) * Nmax + m] = std::sin(ang);
+    }
+
+  GLTable gl{};
+  const int orders[4] = {8, 6, 4, 3};
+  for (int b = 0; b < 4; ++b) {
+    double x[8], w[8];
+    gauss_legendre(orders[b], x, w);
+    gl.n[b] = orders[b];
+    for (int i = 0; i < orders[b]; ++i) {
+      gl.u[b][i] = 0.5 * (1.0 + x[i]);
+      gl.w[b][i] = 0.5 * w[i];
+    }
+  }
+
+  // FP64 temporaries (set-up only)
+  const size_t s0 = (size_t)g.nz * g.ny * g.nx;
+  const size_t s1 = (size_t)g.nz * g.ny * g.Kx;
+  const size_t s2 = (size_t)g.nz * g.Kyh * g.Kx;
+  const size_t s3 = (size_t)g.Kzh * g.Kyh * g.Kx;
+  size_t smax = s0;
+  for (size_t v : {s1, s2, s3}) smax = v > smax ? v : smax;
+  double *bufA = nullptr, *bufB = nullptr, *d_trig = nullptr;
+  int rc = DEMAG_OK;
+  do {
+    if ((e = hipMemcpyAsync(d_tw, tw.data(), TW_SIZE * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess) {
+      rc = fail_hip(e, "twiddle upload"); break;
+    }
+    if (hipMalloc(&bufA, 6 * smax * sizeof(double)) != hipSuccess ||
+        hipMalloc(&bufB, 6 * smax * sizeof(double)) != hipSuccess ||
+        hipMalloc(&d_trig, trig.size() * sizeof(double)) != hipSuccess) {
+      rc = fail(DEMAG_ENOMEM, "demag_bind: set-up temporaries could not be allocated"); break;
+    }
+    if ((e = hipMemcpyAsync(d_trig, trig.data(), trig.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess) {
+      rc = fail_hip(e, "trig upload"); break;
+    }
+    const double* cs[3];
+    const double* sn[3];
+    for (int a = 0; a < 3; ++a) {
+      cs[a] = d_trig + (size_t)(2 * a) * Nmax;
+      sn[a] = d_trig + (size_t)(2 * a + 1) * Nmax;
+    }
+    // component order xx yy zz xy xz yz; odd along x: xy xz; y: xy yz; z: xz yz
+    if ((e = launch_tensor(bufA, g, gl, s)) != hipSuccess) { rc = fail_hip(e, "tensor kernel"); break; }
+    if ((e = launch_axis(bufA, bufB, g.nz * g.ny, g.nx, g.Kx, 1, g.Nx, 0x18u, cs[0], sn[0], s)) != hipSuccess) {
+      rc = fail_hip(e, "x transform"); break;
+    }
+    if ((e = launch_axis(bufB, bufA, g.nz, g.ny, g.Kyh, g.Kx, g.Ny, 0x28u, cs[1], sn[1], s)) != hipSuccess) {
+      rc = fail_hip(e, "y transform"); break;
+    }
+    if ((e = launch_axis(bufA, bufB, 1, g.nz, g.Kzh, g.Kyh * g.Kx, g.Nz, 0x30u, cs[2], sn[2], s)) != hipSuccess) {
+      rc = fail_hip(e, "z transform"); break;
+    }
+    if ((e = launch_pack(bufB, d_K, g, s)) != hipSuccess) { rc = fail_hip(e, "pack"); break; }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) { rc = fail_hip(e, "set-up"); break; }
+  } while (false);
+  if (bufA) (void)hipFree(bufA);
+  if (bufB) (void)hipFree(bufB);
+  if (d_trig) (void)hipFree(d_trig);
+  if (rc != DEMAG_OK) return rc;
+
+  p->tw = d_tw;
+  p->K = d_K;
+  p->T = static_cast<float2*>(d_work);
+  p->epart = reinterpret_cast<double*>(static_cast<char*>(d_work) + align256(spectrum_elems(g) * sizeof(float2)));
+  p->bound = true;
+  return DEMAG_OK;
+}
+
+static int mark(const demag_plan* p, int i, hipStream_t s) {
+  if (!p->timing) return DEMAG_OK;
+  hipError_t e = hipEventRecord(p->ev[i], s);
+  return e == hipSuccess ? DEMAG_OK : fail_hip(e, "hipEventRecord");
+}
+
+static int run_conv(const demag_plan* p, const float* src, const float* Ms, float ms, double* epart, hipStream_t s) {
+  const Geom& g = p->g;
+  int rc = mark(p, 0, s);
+  if (rc != DEMAG_OK) return rc;
+  FwdArgs fa{src, Ms, ms, p->T, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg};
+  hipError_t e = launch_fwd(g, fa, s);
+  if (e != hipSuccess) return fail_hip(e, "forward pass");
+  if ((rc = mark(p, 1, s)) != DEMAG_OK) return rc;
+  MidArgs ma{p->T, p->K, p->tw, epart, g.ny, g.Nz, g.Nx, g.nTiles, g.Kx, g.Kyh, g.Kzh, TILE / mid_kw(g)};
+  e = launch_mid(g, ma, s);
+  if (e != hipSuccess) return fail_hip(e, "middle pass");
+  return mark(p, 2, s);
+}
+
+int demag_field(const demag_plan* p, const float* d_m, const float* d_Ms, float Ms, float* d_H, unsigned flags,
+                double* d_energy, void* stream) {
+  if (!p) return fail(DEMAG_EINVAL, "demag_field: plan is NULL");
+  if (!p->bound) return fail(DEMAG_ESTATE, "demag_field: plan is not bound");
+  if (!d_m || !d_H) return fail(DEMAG_EINVAL, "demag_field: NULL m or H");
+  if (flags & ~(unsigned)DEMAG_ACCUMULATE) return fail(DEMAG_EINVAL, "demag_field: unknown flags");
+  if (!d_Ms && !std::isfinite(Ms)) return fail(DEMAG_EINVAL, "demag_field: Ms is not finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Geom& g = p->g;
+  int rc = run_conv(p, d_m, d_Ms, Ms, d_energy ? p->epart : nullptr, s);
+  if (rc != DEMAG_OK) return rc;
+  InvArgs ia{p->T, d_H, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, (flags & DEMAG_ACCUMULATE) ? 1 : 0,
+             nullptr, nullptr, 0.0, nullptr, 0.f, 0};
+  hipError_t e = launch_inv(g, ia, s);
+  if (e != hipSuccess) return fail_hip(e, "inverse pass");
+  if ((rc = mark(p, 3, s)) != DEMAG_OK) return rc;
+  if (d_energy) {
+    const double V = g.dx * g.dy * g.dz;
+    e = launch_energy_final(p->epart, mid_blocks(g), -0.5 * MU0 * V, d_energy, s);
+    if (e != hipSuccess) return fail_hip(e, "energy reduction");
+  }
+  return DEMAG_OK;
+}
+
+int demag_energy(const demag_plan* p, const float* d_m, const float* d_Ms, float Ms, const float* d_H,
+                 double* d_energy, void* stream) {
+  if (!p) return fail(DEMAG_EINVAL, "demag_energy: plan is NULL");
+  if (!p->bound) return fail(DEMAG_ESTATE, "demag_energy: plan is not bound");
+  if (!d_m || !d_H || !d_energy) return fail(DEMAG_EINVAL, "demag_energy: NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Geom& g = p->g;
+  const size_t ncell = (size_t)g.nx * g.ny * g.nz;
+  hipError_t e = launch_energy_cells(d_m, d_Ms, Ms, d_H, ncell, p->epart, s);
+  if (e != hipSuccess) return fail_hip(e, "energy partials");
+  const double V = g.dx * g.dy * g.dz;
+  e = launch_energy_final(p->epart, energy_cell_blocks(ncell), -0.5 * MU0 * V, d_energy, s);
+  if (e != hipSuccess) return fail_hip(e, "energy reduction");
+  return DEMAG_OK;
+}
+
+int demag_backward(const demag_plan* p, const float* d_G, const float* d_Ms, float Ms, const float* d_H,
+                   const double* d_gE, float* d_grad_m, unsigned flags, void* stream) {
+  if (!p) return fail(DEMAG_EINVAL, "demag_backward: plan is NULL");
+  if (!p->bound) return fail(DEMAG_ESTATE, "demag_backward: plan is not bound");
+  if (!d_G || !d_grad_m) return fail(DEMAG_EINVAL, "demag_backward: NULL G or grad_m");
+  if (d_gE && !d_H) return fail(DEMAG_EINVAL, "demag_backward: the energy term needs the forward field H");
+  if (flags & ~(unsigned)DEMAG_ACCUMULATE) return fail(DEMAG_EINVAL, "demag_backward: unknown flags");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Geom& g = p->g;
+  int rc = run_conv(p, d_G, nullptr, 1.0f, nullptr, s);
+  if (rc != DEMAG_OK) return rc;
+  const double V = g.dx * g.dy * g.dz;
+  InvArgs ia{p->T, d_grad_m, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, (flags & DEMAG_ACCUMULATE) ? 1 : 0,
+             d_H, d_gE, -MU0 * V, d_Ms, Ms, 1};
+  hipError_t e = launch_inv(g, ia, s);
+  if (e != hipSuccess) return fail_hip(e, "inverse pass");
+  return mark(p, 3, s);
+}
+
+int demag_set_timing_events(demag_plan* p, void* const* events, int count) {
+  if (!p) return fail(DEMAG_EINVAL, "demag_set_timing_events: plan is NULL");
+  if (!events || count == 0) {
+    p->timing = false;
+    return DEMAG_OK;
+  }
+  if (count != 4) return fail(DEMAG_EINVAL, "demag_set_timing_events: expected 4 events");
+  for (int i = 0; i < 4; ++i) {
+    if (!events[i]) return fail(DEMAG_EINVAL, "demag_set_timing_events: NULL event");
+    p->ev[i] = static_cast<hipEvent_t>(events[i]);
+  }
+  p->timing = true;
+  return DEMAG_OK;
+}
+
+int demag_destroy(demag_plan* p) {
+  delete p;
+  return DEMAG_OK;
+}
+
+}  // extern "C"

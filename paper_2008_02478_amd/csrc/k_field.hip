@@ -1,0 +1,604 @@
+// Field passes of H = -N * M by zero-padded FFT convolution (Sec. 7: 1D
+// transforms along x, y, z, point-wise product with the transformed kernel,
+// inverse transforms; Sec. 3 Eq. 4 and Table 1 for the sum itself).
+//
+//   k_fwd_xz : per (y rows, component): M = Ms m, real-to-complex FFT along x
+//              (two-for-one packing), then the z FFT per kx; writes the
+//              spectrum T[c][kz][tile][y][8].
+//   k_mid    : per (kz, kx tile): y FFT of the three components, 3x3 product
+//              with the real kernel spectrum (plus Parseval energy partials),
+//              inverse y FFT, in place in T.
+//   k_inv_zx : per (y rows, component): inverse z FFT keeping z < nz, then the
+//              complex-to-real inverse along x keeping x < nx; stores H.
+//
+// Zero padding is never transformed: every padded axis of length N has at most
+// N/2 non-zero inputs, so its FFT splits into the even and odd output residues,
+// each an N/2-point FFT of the (pre-twiddled) non-zero half; the inverse keeps
+// only the first N/2 outputs, which is the sum of the two residue inverses.
+#include "fft_core.hpp"
+#include "plan.hpp"
+
+namespace demag {
+
+// ---------------------------------------------------------------------------
+// forward: x real-to-complex + z
+// ---------------------------------------------------------------------------
+template <int LNX, int LNZ>
+__global__ void __launch_bounds__(FWD_THREADS) k_fwd_xz(FwdArgs a) {
+  constexpr int NX = 1 << LNX;
+  constexpr int NZ = 1 << LNZ;
+  extern __shared__ float2 smem[];
+  const int c = blockIdx.y;
+  const int y0 = blockIdx.x * a.yg;
+  const int yg = min(a.yg, a.ny - y0);
+  const int nz = a.nz, nx = a.nx, ny = a.ny;
+  const int rows = yg * nz;
+  const int tid = threadIdx.x;
+  constexpr int L = (NX >= 4) ? NX / 2 : 1;   // packed complex length
+  constexpr int PITCH = L + 1;                // kx slots per row in LDS
+  const float* msrow = nullptr;
+
+  if constexpr (NX == 1) {
+    for (int row = tid; row < rows; row += FWD_THREADS) {
+      const int yl = row / nz, z = row - yl * nz;
+      const size_t off = ((size_t)z * ny + (y0 + yl)) * nx;
+      const float ms = a.Ms ? a.Ms[off] : a.ms;
+      smem[row * PITCH] = make_float2(a.m[(size_t)c * nz * ny * nx + off] * ms, 0.f);
+    }
+  } else {
+    constexpr int P = L / 2;                  // residue sub-FFT length
+    constexpr int R = LineShape<P>::R;
+    constexpr int T = LineShape<P>::T;
+    constexpr int RPR = FWD_THREADS / (2 * T);
+    const int sub = tid / (2 * T);
+    const int r = (tid / T) & 1;
+    const int t = tid % T;
+    for (int start = 0; start < rows; start += RPR) {
+      const int row = start + sub;
+      const bool act = row < rows;
+      float2* rb = smem + row * PITCH;
+      float2 u[R];
+      if (act) {
+        const int yl = row / nz, z = row - yl * nz;
+        const size_t off = ((size_t)z * ny + (y0 + yl)) * nx;
+        const float* src = a.m + (size_t)c * nz * ny * nx + off;
+        msrow = a.Ms ? a.Ms + off : nullptr;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          const int mm = t + T * j;
+          const int xi = 2 * mm;
+          float v0 = 0.f, v1 = 0.f;
+          if (xi < nx) v0 = src[xi] * (msrow ? msrow[xi] : a.ms);
+          if (xi + 1 < nx) v1 = src[xi + 1] * (msrow ? msrow[xi + 1] : a.ms);
+          float2 val = make_float2(v0, v1);
+          if (r) val = cmul(val, twiddle<false>(a.tw, mm, LNX - 1));
+          u[j] = val;
+        }
+        group_fft<P, R, false>(u, rb + r * P, t, a.tw);
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) rb[2 * (t + T * j) + r] = u[j];
+      }
+      __syncthreads();
+      if (act) {
+        // X[k] = E + W^k O and X[L-k] = conj(E - W^k O), with
+        // E = (U[k] + conj U[L-k]) / 2 and O = -i (U[k] - conj U[L-k]) / 2.
+        for (int k = tid % (2 * T); k <= L / 2; k += 2 * T) {
+          const float2 Uk = rb[k];
+          const float2 Um = rb[(L - k) & (L - 1)];
+          const float2 E = make_float2(0.5f * (Uk.x + Um.x), 0.5f * (Uk.y - Um.y));
+          const float2 O = make_float2(0.5f * (Uk.y + Um.y), -0.5f * (Uk.x - Um.x));
+          const float2 WO = cmul(O, twiddle<false>(a.tw, k, LNX));
+          if (k == 0) {
+            rb[0] = make_float2(E.x + O.x, E.y + O.y);
+            rb[L] = make_float2(E.x - O.x, E.y - O.y);
+          } else {
+            rb[k] = cadd(E, WO);
+            if (k != L - k) rb[L - k] = cconj(csub(E, WO));
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+
+  // z transform per (y, kx) and store of the spectrum
+  const int Kx = a.Kx;
+  const int items = yg * Kx;
+  for (int it = tid; it < items; it += FWD_THREADS) {
+    const int yl = it / Kx, kx = it - yl * Kx;
+    const int y = y0 + yl;
+    float2* dst = a.T + ((((size_t)c * NZ) * a.nTiles + kx / TILE) * ny + y) * TILE + (kx % TILE);
+    const size_t kzstride = (size_t)a.nTiles * ny * TILE;
+    if constexpr (NZ == 1) {
+      dst[0] = smem[(yl * nz) * PITCH + kx];
+    } else {
+      constexpr int Q = NZ / 2;
+      float2 xz[Q];
+#pragma unroll
+      for (int z = 0; z < Q; ++z)
+        xz[z] = (z < nz) ? smem[(yl * nz + z) * PITCH + kx] : make_float2(0.f, 0.f);
+      float2 v[Q];
+#pragma unroll
+      for (int z = 0; z < Q; ++z) v[z] = xz[z];
+      dft<Q, false>(v);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) dst[(size_t)(2 * k) * kzstride] = v[k];
+#pragma unroll
+      for (int z = 0; z < Q; ++z) v[z] = cmul(xz[z], twiddle<false>(a.tw, z, LNZ));
+      dft<Q, false>(v);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) dst[(size_t)(2 * k + 1) * kzstride] = v[k];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// middle: y FFT, kernel product, inverse y FFT
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_logical(int b, int nblk) {
+  // workgroups are handed to the 8 XCDs round-robin; give each XCD a
+  // contiguous range of logical work so neighbours share its L2
+  const int x = b & 7, idx = b >> 3;
+  const int per = nblk >> 3, rem = nblk & 7;
+  return x * per + min(x, rem) + idx;
+}
+
+__device__ __forceinline__ int kz_of(int i, int Nz) {
+  // 0, Nz/2, 1, Nz-1, 2, Nz-2, ...: +-kz share kernel lines
+  if (Nz == 1) return 0;
+  if (i == 0) return 0;
+  if (i == 1) return Nz / 2;
+  const int p = (i - 2) / 2 + 1;
+  return (i & 1) ? Nz - p : p;
+}
+
+// threads of the middle pass: two residue jobs per kx (one for a unit y
+// length), each a group of LineShape<M>::T lanes, at least one wavefront
+constexpr int mid_threads(int lny, int kw) {
+  const int ny = 1 << lny;
+  const int m = ny > 1 ? ny / 2 : 1;
+  const int r = m >= 1024 ? 16 : (m >= 8 ? 8 : m);
+  const int nt = (ny > 1 ? 2 : 1) * kw * (m / r);
+  return nt < 64 ? 64 : nt;
+}
+
+template <typename Tv>
+__device__ __forceinline__ Tv block_sum(Tv v, Tv* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  Tv s = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+  return s;
+}
+
+template <int LNY, int KW>
+__global__ void __launch_bounds__(mid_threads(LNY, KW))
+k_mid(MidArgs a) {
+  constexpr int NY = 1 << LNY;
+  constexpr int M = NY > 1 ? NY / 2 : 1;
+  constexpr int NRES = NY > 1 ? 2 : 1;
+  constexpr int R = LineShape<M>::R;
+  constexpr int T = LineShape<M>::T;
+  constexpr int JOBS = NRES * KW;
+  constexpr int NT = JOBS * T;
+  __shared__ double red[16];
+  extern __shared__ float2 smem[];
+
+  const int nblk = gridDim.x;
+  const int lg = xcd_logical(blockIdx.x, nblk);
+  const int halves = a.kw_halves;
+  const int half = lg % halves;
+  const int kzi = (lg / halves) % a.Nz;
+  const int tile = lg / (halves * a.Nz);
+  const int kz = kz_of(kzi, a.Nz);
+  const int ny = a.ny;
+
+  const int tid = threadIdx.x;
+  const bool lane_act = tid < NT;
+  const int job = tid / T, t = tid % T;
+  const int w = job / NRES, r = job % NRES;
+  const int kx = tile * TILE + half * KW + w;
+  const bool valid = lane_act && kx < a.Kx;
+  float2* stage = smem;                     // ny * KW points
+  float2* scr = smem + (size_t)job * M;     // M points per job (aliases stage)
+  const size_t cstride = (size_t)a.Nz * a.nTiles * ny * TILE;
+  float2* blk0 = a.T + ((size_t)kz * a.nTiles + tile) * ny * TILE + half * KW;
+
+  float2 v[3][R];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float2* blk = blk0 + c * cstride;
+    __syncthreads();
+    for (int e = tid; e < ny * KW; e += blockDim.x) {
+      const int y = e / KW, q = e - y * KW;
+      stage[e] = blk[(size_t)y * TILE + q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int y = t + T * j;
+      float2 val = (valid && y < ny) ? stage[y * KW + w] : make_float2(0.f, 0.f);
+      if (NRES == 2 && r) val = cmul(val, twiddle<false>(a.tw, y, LNY));
+      v[c][j] = val;
+    }
+  }
+  __syncthreads();
+  if (lane_act) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) group_fft<M, R, false>(v[c], scr, t, a.tw);
+  }
+
+  // point-wise product with the real, symmetric kernel spectrum
+  double e = 0.0;
+  if (lane_act) {
+    const int kzf = (kz <= a.Nz / 2) ? kz : a.Nz - kz;
+    const float sz = (kz <= a.Nz / 2) ? 1.f : -1.f;
+    const int kxc = min(kx, a.Kx - 1);
+    const float* Kb = a.K + ((size_t)kzf * a.Kx + kxc) * 6 * a.Kyh;
+    const float wkx = (kx == 0 || 2 * kx == a.Nx) ? 1.f : 2.f;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int ky = NRES * (t + T * j) + r;
+      const bool lo = 2 * ky <= NY;
+      const int kyf = lo ? ky : NY - ky;
+      const float sy = lo ? 1.f : -1.f;
+      const float kxx = Kb[0 * a.Kyh + kyf];
+      const float kyy = Kb[1 * a.Kyh + kyf];
+      const float kzz = Kb[2 * a.Kyh + kyf];
+      const float kxy = sy * Kb[3 * a.Kyh + kyf];
+      const float kxz = sz * Kb[4 * a.Kyh + kyf];
+      const float kyz = sy * sz * Kb[5 * a.Kyh + kyf];
+      const float2 mx = v[0][j], my = v[1][j], mz = v[2][j];
+      const float2 hx = make_float2(kxx * mx.x + kxy * my.x + kxz * mz.x, kxx * mx.y + kxy * my.y + kxz * mz.y);
+      const float2 hy = make_float2(kxy * mx.x + kyy * my.x + kyz * mz.x, kxy * mx.y + kyy * my.y + kyz * mz.y);
+      const float2 hz = make_float2(kxz * mx.x + kyz * my.x + kzz * mz.x, kxz * mx.y + kyz * my.y + kzz * mz.y);
+      if (a.epart && valid) {
+        const float d = mx.x * hx.x + mx.y * hx.y + my.x * hy.x + my.y * hy.y + mz.x * hz.x + mz.y * hz.y;
+        e += (double)(wkx * d);
+      }
+      v[0][j] = hx; v[1][j] = hy; v[2][j] = hz;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      group_fft<M, R, true>(v[c], scr, t, a.tw);
+      if (NRES == 2 && r) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) v[c][j] = cmul(v[c][j], twiddle<true>(a.tw, t + T * j, LNY));
+      }
+    }
+  }
+
+  // sum the two residues and store
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float2* blk = blk0 + c * cstride;
+    __syncthreads();
+    if (lane_act && r == NRES - 1) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int y = t + T * j;
+        if (y < ny) stage[y * KW + w] = v[c][j];
+      }
+    }
+    __syncthreads();
+    if constexpr (NRES == 2) {
+      if (lane_act && r == 0) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          const int y = t + T * j;
+          if (y < ny) stage[y * KW + w] = cadd(stage[y * KW + w], v[c][j]);
+        }
+      }
+      __syncthreads();
+    }
+    for (int q = tid; q < ny * KW; q += blockDim.x) {
+      const int y = q / KW, s = q - y * KW;
+      blk[(size_t)y * TILE + s] = stage[q];
+    }
+  }
+  if (a.epart) {
+    const double s = block_sum(e, red);
+    if (tid == 0) a.epart[lg] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// inverse: z + x complex-to-real
+// ---------------------------------------------------------------------------
+template <int LNX, int LNZ>
+__global__ void __launch_bounds__(INV_THREADS) k_inv_zx(InvArgs a) {
+  constexpr int NX = 1 << LNX;
+  constexpr int NZ = 1 << LNZ;
+  extern __shared__ float2 smem[];
+  const int c = blockIdx.y;
+  const int y0 = blockIdx.x * a.yg;
+  const int yg = min(a.yg, a.ny - y0);
+  const int nz = a.nz, nx = a.nx, ny = a.ny;
+  const int rows = yg * nz;
+  const int tid = threadIdx.x;
+  constexpr int L = (NX >= 4) ? NX / 2 : 1;
+  constexpr int PITCH = L + 1;
+  const int Kx = a.Kx;
+
+  // inverse z per (y, kx), keeping z < nz
+  const int items = yg * Kx;
+  for (int it = tid; it < items; it += INV_THREADS) {
+    const int yl = it / Kx, kx = it - yl * Kx;
+    const int y = y0 + yl;
+    const float2* src = a.T + ((((size_t)c * NZ) * a.nTiles + kx / TILE) * ny + y) * TILE + (kx % TILE);
+    const size_t kzstride = (size_t)a.nTiles * ny * TILE;
+    if constexpr (NZ == 1) {
+      smem[(yl * nz) * PITCH + kx] = src[0];
+    } else {
+      constexpr int Q = NZ / 2;
+      float2 ve[Q], vo[Q];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        ve[k] = src[(size_t)(2 * k) * kzstride];
+        vo[k] = src[(size_t)(2 * k + 1) * kzstride];
+      }
+      dft<Q, true>(ve);
+      dft<Q, true>(vo);
+#pragma unroll
+      for (int z = 0; z < Q; ++z) {
+        if (z < nz)
+          smem[(yl * nz + z) * PITCH + kx] = cadd(ve[z], cmul(vo[z], twiddle<true>(a.tw, z, LNZ)));
+      }
+    }
+  }
+  __syncthreads();
+
+  const size_t cbase = (size_t)c * nz * ny * nx;
+  if constexpr (NX == 1) {
+    for (int row = tid; row < rows; row += INV_THREADS) {
+      const int yl = row / nz, z = row - yl * nz;
+      const size_t off = ((size_t)z * ny + (y0 + yl)) * nx;
+      float val = smem[row * PITCH].x;
+      if (a.scale_out) {
+        const float s = a.Ms ? a.Ms[off] : a.ms;
+        val = s * (val + (a.beta_ptr ? (float)(a.beta_scale * *a.beta_ptr) * a.aux[cbase + off] : 0.f));
+      }
+      float* dst = a.H + cbase + off;
+      dst[0] = a.accumulate ? dst[0] + val : val;
+    }
+  } else {
+    constexpr int P = L / 2;
+    constexpr int R = LineShape<P>::R;
+    constexpr int T = LineShape<P>::T;
+    constexpr int RPR = INV_THREADS / (2 * T);
+    const int sub = tid / (2 * T);
+    const int r = (tid / T) & 1;
+    const int t = tid % T;
+    const float beta = (a.scale_out && a.beta_ptr) ? (float)(a.beta_scale * *a.beta_ptr) : 0.f;
+    for (int start = 0; start < rows; start += RPR) {
+      const int row = start + sub;
+      const bool act = row < rows;
+      float2* rb = smem + row * PITCH;
+      float2 u[R];
+      if (act) {
+        // U[k] = (X[k] + conj X[L-k]) + i W^-k (X[k] - conj X[L-k]); inverse
+        // of the packed FFT of (x[2m], x[2m+1]), scaled to match X
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          const int k = 2 * (t + T * j) + r;
+          const float2 Xk = rb[k];
+          const float2 Xm = rb[L - k];
+          const float2 S = make_float2(Xk.x + Xm.x, Xk.y - Xm.y);
+          const float2 D = make_float2(Xk.x - Xm.x, Xk.y + Xm.y);
+          const float2 WD = cmul(D, twiddle<true>(a.tw, k, LNX));
+          u[j] = make_float2(S.x - WD.y, S.y + WD.x);
+        }
+      }
+      __syncthreads();
+      if (act) {
+        group_fft<P, R, true>(u, rb + r * P, t, a.tw);
+        if (r) {
+#pragma unroll
+          for (int j = 0; j < R; ++j) u[j] = cmul(u[j], twiddle<true>(a.tw, t + T * j, LNX - 1));
+        }
+      }
+      __syncthreads();
+      if (act && r == 1) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) rb[t + T * j] = u[j];
+      }
+      __syncthreads();
+      if (act && r == 0) {
+        const int yl = row / nz, z = row - yl * nz;
+        const size_t off = ((size_t)z * ny + (y0 + yl)) * nx;
+        float* dst = a.H + cbase + off;
+        const float* aux = a.scale_out ? a.aux + cbase + off : nullptr;
+        const float* msr = (a.scale_out && a.Ms) ? a.Ms + off : nullptr;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          const int mm = t + T * j;
+          const float2 uu = cadd(u[j], rb[mm]);
+          const int xi = 2 * mm;
+          float v0 = uu.x, v1 = uu.y;
+          if (a.scale_out) {
+            if (xi < nx) v0 = (msr ? msr[xi] : a.ms) * (v0 + (a.beta_ptr ? beta * aux[xi] : 0.f));
+            if (xi + 1 < nx) v1 = (msr ? msr[xi + 1] : a.ms) * (v1 + (a.beta_ptr ? beta * aux[xi + 1] : 0.f));
+          }
+          if (xi < nx) dst[xi] = a.accumulate ? dst[xi] + v0 : v0;
+          if (xi + 1 < nx) dst[xi + 1] = a.accumulate ? dst[xi + 1] + v1 : v1;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// energy reductions
+// ---------------------------------------------------------------------------
+// Sum of the middle pass' Parseval partials in a fixed order:
+// E = scale * sum(partials), scale = -(mu0/2) V.
+__global__ void __launch_bounds__(RED_THREADS) k_energy_final(const double* part, int n, double scale,
+                                                              double* out) {
+  __shared__ double red[RED_THREADS / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += RED_THREADS) s += part[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) *out = scale * s;
+}
+
+// Per-workgroup partials of sum_c Ms m_c H_c over the cells.
+__global__ void __launch_bounds__(RED_THREADS) k_energy_cells(const float* m, const float* Ms, float ms,
+                                                              const float* H, size_t ncell, double* part) {
+  __shared__ double red[RED_THREADS / 64];
+  double s = 0.0;
+  for (size_t i = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; i < ncell; i += (size_t)gridDim.x * RED_THREADS) {
+    const float msv = Ms ? Ms[i] : ms;
+    const float d = m[i] * H[i] + m[ncell + i] * H[ncell + i] + m[2 * ncell + i] * H[2 * ncell + i];
+    s += (double)(msv * d);
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+}  // namespace demag
+
+// ---------------------------------------------------------------------------
+// host-side launchers (compile-time FFT lengths dispatched from the plan)
+// ---------------------------------------------------------------------------
+#include "launch.hpp"
+
+namespace demag {
+
+static size_t xpass_lds(const Geom& g) {
+  const int pitch = (g.Nx >= 4 ? g.Nx / 2 : 1) + 1;
+  return (size_t)g.yg * g.nz * pitch * sizeof(float2);
+}
+
+template <typename K>
+static hipError_t prep_lds(K kern, size_t lds) {
+  if (lds > 65536)
+    return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return hipSuccess;
+}
+
+template <int LNX, int LNZ>
+static hipError_t fwd_one(const Geom& g, const FwdArgs& a, hipStream_t s) {
+  const size_t lds = xpass_lds(g);
+  hipError_t e = prep_lds(k_fwd_xz<LNX, LNZ>, lds);
+  if (e != hipSuccess) return e;
+  dim3 grid((g.ny + g.yg - 1) / g.yg, 3);
+  hipLaunchKernelGGL((k_fwd_xz<LNX, LNZ>), grid, dim3(FWD_THREADS), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int LNX, int LNZ>
+static hipError_t inv_one(const Geom& g, const InvArgs& a, hipStream_t s) {
+  const size_t lds = xpass_lds(g);
+  hipError_t e = prep_lds(k_inv_zx<LNX, LNZ>, lds);
+  if (e != hipSuccess) return e;
+  dim3 grid((g.ny + g.yg - 1) / g.yg, 3);
+  hipLaunchKernelGGL((k_inv_zx<LNX, LNZ>), grid, dim3(INV_THREADS), lds, s, a);
+  return hipGetLastError();
+}
+
+#define DEMAG_Z_SWITCH(FN, LNX, ...)                      \
+  switch (g.lnz) {                                        \
+    case 0: return FN<LNX, 0>(__VA_ARGS__);               \
+    case 2: return FN<LNX, 2>(__VA_ARGS__);               \
+    case 3: return FN<LNX, 3>(__VA_ARGS__);               \
+    case 4: return FN<LNX, 4>(__VA_ARGS__);               \
+    case 5: return FN<LNX, 5>(__VA_ARGS__);               \
+    default: return hipErrorInvalidValue;                 \
+  }
+
+template <int LNX>
+static hipError_t fwd_z(const Geom& g, const FwdArgs& a, hipStream_t s) { DEMAG_Z_SWITCH(fwd_one, LNX, g, a, s) }
+template <int LNX>
+static hipError_t inv_z(const Geom& g, const InvArgs& a, hipStream_t s) { DEMAG_Z_SWITCH(inv_one, LNX, g, a, s) }
+
+#define DEMAG_X_SWITCH(FN, ...)                           \
+  switch (g.lnx) {                                        \
+    case 0: return FN<0>(__VA_ARGS__);                    \
+    case 2: return FN<2>(__VA_ARGS__);                    \
+    case 3: return FN<3>(__VA_ARGS__);                    \
+    case 4: return FN<4>(__VA_ARGS__);                    \
+    case 5: return FN<5>(__VA_ARGS__);                    \
+    case 6: return FN<6>(__VA_ARGS__);                    \
+    case 7: return FN<7>(__VA_ARGS__);                    \
+    case 8: return FN<8>(__VA_ARGS__);                    \
+    case 9: return FN<9>(__VA_ARGS__);                    \
+    case 10: return FN<10>(__VA_ARGS__);                  \
+    case 11: return FN<11>(__VA_ARGS__);                  \
+    case 12: return FN<12>(__VA_ARGS__);                  \
+    default: return hipErrorInvalidValue;                 \
+  }
+
+hipError_t launch_fwd(const Geom& g, const FwdArgs& a, hipStream_t s) { DEMAG_X_SWITCH(fwd_z, g, a, s) }
+hipError_t launch_inv(const Geom& g, const InvArgs& a, hipStream_t s) { DEMAG_X_SWITCH(inv_z, g, a, s) }
+
+int mid_kw(const Geom& g) {
+  const int M = g.Ny > 1 ? g.Ny / 2 : 1;
+  return (2 * 8 * (size_t)M * sizeof(float2) <= 65536) ? 8 : 4;
+}
+
+int mid_blocks(const Geom& g) { return g.nTiles * (TILE / mid_kw(g)) * g.Nz; }
+
+template <int LNY, int KW>
+static hipError_t mid_one(const Geom& g, const MidArgs& a, hipStream_t s) {
+  constexpr int NY = 1 << LNY;
+  constexpr int M = NY > 1 ? NY / 2 : 1;
+  constexpr int NRES = NY > 1 ? 2 : 1;
+  size_t lds = (size_t)NRES * KW * M * sizeof(float2);
+  const size_t st = (size_t)g.ny * KW * sizeof(float2);
+  if (st > lds) lds = st;
+  hipError_t e = prep_lds(k_mid<LNY, KW>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_mid<LNY, KW>), dim3(mid_blocks(g)), dim3(mid_threads(LNY, KW)), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int LNY>
+static hipError_t mid_kw_switch(const Geom& g, const MidArgs& a, hipStream_t s) {
+  if (mid_kw(g) == 8) return mid_one<LNY, 8>(g, a, s);
+  return mid_one<LNY, 4>(g, a, s);
+}
+
+hipError_t launch_mid(const Geom& g, const MidArgs& a, hipStream_t s) {
+  switch (g.lny) {
+    case 0: return mid_kw_switch<0>(g, a, s);
+    case 2: return mid_kw_switch<2>(g, a, s);
+    case 3: return mid_kw_switch<3>(g, a, s);
+    case 4: return mid_kw_switch<4>(g, a, s);
+    case 5: return mid_kw_switch<5>(g, a, s);
+    case 6: return mid_kw_switch<6>(g, a, s);
+    case 7: return mid_kw_switch<7>(g, a, s);
+    case 8: return mid_kw_switch<8>(g, a, s);
+    case 9: return mid_kw_switch<9>(g, a, s);
+    case 10: return mid_kw_switch<10>(g, a, s);
+    case 11: return mid_kw_switch<11>(g, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_energy_final(const double* part, int n, double scale, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(RED_THREADS), 0, s, part, n, scale, out);
+  return hipGetLastError();
+}
+
+int energy_cell_blocks(size_t ncell) {
+  size_t b = (ncell + RED_THREADS - 1) / RED_THREADS;
+  return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
+}
+
+hipError_t launch_energy_cells(const float* m, const float* Ms, float ms, const float* H, size_t ncell,
+                               double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_cells, dim3(energy_cell_blocks(ncell)), dim3(RED_THREADS), 0, s, m, Ms, ms, H,
+                     ncell, part);
+  return hipGetLastError();
+}
+
+}  // namespace demag

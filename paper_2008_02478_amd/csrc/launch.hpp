@@ -1,0 +1,24 @@
+// Host launchers of the demagnetizing-field kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "plan.hpp"
+
+namespace demag {
+
+hipError_t launch_fwd(const Geom& g, const FwdArgs& a, hipStream_t s);
+hipError_t launch_mid(const Geom& g, const MidArgs& a, hipStream_t s);
+hipError_t launch_inv(const Geom& g, const InvArgs& a, hipStream_t s);
+hipError_t launch_energy_final(const double* part, int n, double scale, double* out, hipStream_t s);
+hipError_t launch_energy_cells(const float* m, const float* Ms, float ms, const float* H, size_t ncell,
+                               double* part, hipStream_t s);
+int mid_kw(const Geom& g);
+int mid_blocks(const Geom& g);
+int energy_cell_blocks(size_t ncell);
+
+struct GLTable;
+hipError_t launch_tensor(double* out, const Geom& g, const GLTable& gl, hipStream_t s);
+hipError_t launch_axis(const double* in, double* out, int outer, int nin, int nout, int inner, int npad,
+                       unsigned odd_mask, const double* cs, const double* sn, hipStream_t s);
+hipError_t launch_pack(const double* in, float* K, const Geom& g, hipStream_t s);
+
+}  // namespace demag

@@ -1,0 +1,141 @@
+"""PyTorch front end of the demagnetizing-field library.
+
+PyTorch supplies device memory and the current stream; the arithmetic runs
+in the library (include/demag.h).  A DemagPlan owns the plan and the two
+device buffers it needs.
+"""
+import ctypes
+import math
+
+import torch
+
+from . import lib as _l
+
+MU0 = 4e-7 * math.pi
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class DemagPlan:
+    """Plan for one mesh of n = (nx, ny, nz) cells of size cell = (dx, dy, dz)
+    metres with open boundaries.  Builds the kernel spectrum on construction."""
+
+    def __init__(self, n, cell, device=None, pbc=0, images=0):
+        self._lib = _l.load()
+        self.n = tuple(int(v) for v in n)
+        self.cell = tuple(float(v) for v in cell)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self._p = ctypes.c_void_p()
+        _l.check(self._lib.demag_setup(ctypes.byref(self._p), *self.n, *self.cell, int(pbc), int(images)))
+        kb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        _l.check(self._lib.demag_buffer_bytes(self._p, ctypes.byref(kb), ctypes.byref(wb)))
+        Nx, Ny, Nz = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _l.check(self._lib.demag_padded_dims(self._p, ctypes.byref(Nx), ctypes.byref(Ny), ctypes.byref(Nz)))
+        self.padded = (Nx.value, Ny.value, Nz.value)
+        self.kernel_bytes, self.work_bytes = kb.value, wb.value
+        with torch.cuda.device(self.device):
+            # over-allocate by 256 bytes and align, the library needs 256-byte alignment
+            self._kbuf = torch.empty(kb.value + 256, dtype=torch.uint8, device=self.device)
+            self._wbuf = torch.empty(wb.value + 256, dtype=torch.uint8, device=self.device)
+            _l.check(self._lib.demag_bind(self._p, self._aligned(self._kbuf), self._aligned(self._wbuf), _stream()))
+
+    @staticmethod
+    def _aligned(buf):
+        a = buf.data_ptr()
+        return ctypes.c_void_p((a + 255) & ~255)
+
+    @property
+    def shape(self):
+        nx, ny, nz = self.n
+        return (3, nz, ny, nx)
+
+    @property
+    def volume(self):
+        return self.cell[0] * self.cell[1] * self.cell[2]
+
+    def _check_vec(self, t, name):
+        if t.shape != self.shape or t.dtype != torch.float32 or not t.is_contiguous() or t.device != self.device:
+            raise ValueError(f"{name}: expected contiguous float32 {self.shape} on {self.device}, "
+                             f"got {tuple(t.shape)} {t.dtype} on {t.device}")
+
+    def _ms(self, Ms):
+        if isinstance(Ms, torch.Tensor):
+            nx, ny, nz = self.n
+            if Ms.shape != (nz, ny, nx) or Ms.dtype != torch.float32 or not Ms.is_contiguous():
+                raise ValueError("Ms: expected a contiguous float32 (nz, ny, nx) tensor or a float")
+            return Ms, 0.0
+        return None, float(Ms)
+
+    def field(self, m, Ms, out=None, accumulate=False, energy=False):
+        """H_d = -N * (Ms m).  Returns H, or (H, E) with E a 0-d float64 device
+        tensor when energy=True."""
+        self._check_vec(m, "m")
+        if out is None:
+            out = torch.empty_like(m)
+        else:
+            self._check_vec(out, "out")
+        msa, mss = self._ms(Ms)
+        e = torch.empty((), dtype=torch.float64, device=self.device) if energy else None
+        _l.check(self._lib.demag_field(self._p, _ptr(m), _ptr(msa), mss, _ptr(out),
+                                       _l.ACCUMULATE if accumulate else 0, _ptr(e), _stream()))
+        return (out, e) if energy else out
+
+    def energy(self, m, Ms, H):
+        """E = -(mu0/2) V sum Ms m . H as a 0-d float64 device tensor."""
+        self._check_vec(m, "m")
+        self._check_vec(H, "H")
+        msa, mss = self._ms(Ms)
+        e = torch.empty((), dtype=torch.float64, device=self.device)
+        _l.check(self._lib.demag_energy(self._p, _ptr(m), _ptr(msa), mss, _ptr(H), _ptr(e), _stream()))
+        return e
+
+    def backward(self, G, Ms, H=None, gE=None, out=None, accumulate=False):
+        """grad_m of <G, H_d> + gE * E_demag: Ms * (-N * G - mu0 V gE H)."""
+        self._check_vec(G, "G")
+        if out is None:
+            out = torch.empty_like(G)
+        msa, mss = self._ms(Ms)
+        if gE is not None:
+            gE = gE.to(device=self.device, dtype=torch.float64).reshape(()).contiguous()
+            self._check_vec(H, "H")
+        _l.check(self._lib.demag_backward(self._p, _ptr(G), _ptr(msa), mss, _ptr(H) if gE is not None else None,
+                                          _ptr(gE), _ptr(out), _l.ACCUMULATE if accumulate else 0, _stream()))
+        return out
+
+    def __del__(self):
+        p = getattr(self, "_p", None)
+        if p is not None and p.value:
+            self._lib.demag_destroy(p)
+            self._p = None
+
+
+class DemagFunction(torch.autograd.Function):
+    """(H_d, E) = demag(m) for M = Ms m with a hand-written backward: the
+    operator is self-adjoint, so the gradient of <G, H_d> is the same
+    convolution applied to G, and that of E is -mu0 V Ms H_d."""
+
+    @staticmethod
+    def forward(ctx, m, plan, Ms):
+        H, E = plan.field(m.contiguous(), Ms, energy=True)
+        ctx.plan, ctx.Ms = plan, Ms
+        ctx.save_for_backward(H)
+        return H, E
+
+    @staticmethod
+    def backward(ctx, gH, gE):
+        (H,) = ctx.saved_tensors
+        if gH is None:
+            gH = torch.zeros_like(H)
+        grad_m = ctx.plan.backward(gH.contiguous(), ctx.Ms, H=H, gE=gE)
+        return grad_m, None, None
+
+
+def demag(m, plan, Ms):
+    """Differentiable (H_d, E_demag) of a unit magnetization m."""
+    return DemagFunction.apply(m, plan, Ms)

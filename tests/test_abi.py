@@ -1,0 +1,120 @@
+"""The C ABI without a GPU: every symbol declared in include/demag.h is
+exported, and argument checking happens on the host before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2008_02478_amd import lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2008_02478_amd import build_lib
+        build_lib.build()
+    return L.load()
+
+
+def declared():
+    text = open(os.path.join(ROOT, "include", "demag.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(demag_\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert "demag_field" in names and "demag_setup" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def setup(lib, *args):
+    p = ctypes.c_void_p()
+    rc = lib.demag_setup(ctypes.byref(p), *args)
+    return rc, p
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 4, 4, 1e-9, 1e-9, 1e-9, 0, 0), L.EINVAL),
+    ((4, -1, 4, 1e-9, 1e-9, 1e-9, 0, 0), L.EINVAL),
+    ((4, 4, 4, 0.0, 1e-9, 1e-9, 0, 0), L.EINVAL),
+    ((4, 4, 4, 1e-9, float("nan"), 1e-9, 0, 0), L.EINVAL),
+    ((4, 4, 4, 1e-9, 1e-9, float("inf"), 0, 0), L.EINVAL),
+    ((4, 4, 4, 1e-9, 1e-9, 1e-9, 8, 0), L.EINVAL),
+    ((4, 4, 4, 1e-9, 1e-9, 1e-9, L.PBC_X, 3), L.EUNSUPPORTED),
+    ((4, 4, 17, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
+    ((4, 1025, 4, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
+    ((2049, 4, 4, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
+    ((2048, 4, 16, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
+])
+def test_setup_rejects(lib, args, code):
+    rc, p = setup(lib, *args)
+    assert rc == code
+    assert not p.value
+    assert len(lib.demag_last_error()) > 0
+
+
+def test_setup_null_out(lib):
+    assert lib.demag_setup(None, 4, 4, 4, 1e-9, 1e-9, 1e-9, 0, 0) == L.EINVAL
+
+
+@pytest.mark.parametrize("n,padded", [((64, 64, 1), (128, 128, 1)), ((512, 512, 16), (1024, 1024, 32)),
+                                      ((1, 1, 1), (1, 1, 1)), ((5, 3, 2), (16, 8, 4)),
+                                      ((1024, 1024, 4), (2048, 2048, 8))])
+def test_geometry_and_buffer_sizes(lib, n, padded):
+    rc, p = setup(lib, *n, 2e-9, 2e-9, 1e-9, 0, 0)
+    assert rc == L.OK
+    try:
+        dims = [ctypes.c_int() for _ in range(3)]
+        assert lib.demag_padded_dims(p, *[ctypes.byref(d) for d in dims]) == L.OK
+        assert tuple(d.value for d in dims) == padded
+        kb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        assert lib.demag_buffer_bytes(p, ctypes.byref(kb), ctypes.byref(wb)) == L.OK
+        Nx, Ny, Nz = padded
+        Kx = Nx // 2 + 1 if Nx > 1 else 1
+        Ky = Ny // 2 + 1 if Ny > 1 else 1
+        Kz = Nz // 2 + 1 if Nz > 1 else 1
+        assert kb.value >= 6 * Kx * Ky * Kz * 4 + 4096 * 8
+        tiles = (Kx + 7) // 8
+        assert wb.value >= 3 * Nz * tiles * 8 * n[1] * 8
+        assert kb.value % 256 == 0 and wb.value % 256 == 0
+    finally:
+        assert lib.demag_destroy(p) == L.OK
+
+
+def test_calls_before_bind_are_state_errors(lib):
+    rc, p = setup(lib, 8, 8, 2, 1e-9, 1e-9, 1e-9, 0, 0)
+    assert rc == L.OK
+    try:
+        dummy = ctypes.c_void_p(256)
+        assert lib.demag_field(p, dummy, None, 1.0, dummy, 0, None, None) == L.ESTATE
+        assert lib.demag_energy(p, dummy, None, 1.0, dummy, dummy, None) == L.ESTATE
+        assert lib.demag_backward(p, dummy, None, 1.0, None, None, dummy, 0, None) == L.ESTATE
+        # bind validates its buffers before touching the device
+        assert lib.demag_bind(p, None, dummy, None) == L.EINVAL
+        assert lib.demag_bind(p, ctypes.c_void_p(257), dummy, None) == L.EINVAL
+    finally:
+        lib.demag_destroy(p)
+
+
+def test_null_plan_and_destroy(lib):
+    assert lib.demag_destroy(None) == L.OK
+    assert lib.demag_field(None, None, None, 1.0, None, 0, None, None) == L.EINVAL
+    assert lib.demag_buffer_bytes(None, None, None) == L.EINVAL
+    assert lib.demag_set_timing_events(None, None, 0) == L.EINVAL
+
+
+def test_timing_event_validation(lib):
+    rc, p = setup(lib, 8, 8, 2, 1e-9, 1e-9, 1e-9, 0, 0)
+    try:
+        arr = (ctypes.c_void_p * 4)(1, 2, 3, 4)
+        assert lib.demag_set_timing_events(p, arr, 3) == L.EINVAL
+        bad = (ctypes.c_void_p * 4)(1, None, 3, 4)
+        assert lib.demag_set_timing_events(p, bad, 4) == L.EINVAL
+        assert lib.demag_set_timing_events(p, None, 0) == L.OK
+    finally:
+        lib.demag_destroy(p)

@@ -1,0 +1,68 @@
+"""Full-size GPU parity: 512x512x16 and 1024x1024x4 meshes of 2x2x1 nm cells,
+Ms = 1.1e6 A/m, random-domain (Voronoi) fields, in the launch configuration
+the benchmark times.  Every output is compared with the FP64 oracle's FFT
+convolution, a sample of cells with its direct sum, and the uniform-box
+mean field with the prism factors (Aharoni)."""
+import numpy as np
+import pytest
+
+from oracle import conv
+from oracle.newell import tensor_full
+from paper_2008_02478_amd import inputs
+from tests.gpu_common import TOL, rel_l2, require_gpu, say, to_dev
+from tests.test_oracle_tensor import aharoni_diag
+
+pytestmark = pytest.mark.gpu
+
+H_CELL = (2e-9, 2e-9, 1e-9)
+MS = 1.1e6
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.mark.parametrize("n,seed", [((512, 512, 16), 10), ((1024, 1024, 4), 11)])
+def test_full_size(torch, n, seed):
+    from paper_2008_02478_amd.demag import DemagPlan
+    say(f"large {n} voronoi seed {seed}: GPU")
+    m = inputs.voronoi(n, (2, 2, 1), seed=seed)
+    G = inputs.gaussian(n, seed=seed + 100)
+    plan = DemagPlan(n, H_CELL)
+    md, Gd = to_dev(m, torch), to_dev(G, torch)
+    H, E = plan.field(md, MS, energy=True)
+    grad = plan.backward(Gd, MS)
+    Hn, En, gn = H.cpu().numpy(), float(E), grad.cpu().numpy()
+    # uniform magnetization: mean field equals -N_box M (exact, any size)
+    u = np.zeros_like(m)
+    u[0], u[1], u[2] = 0.6, -0.48, 0.64
+    Hu = plan.field(to_dev(u, torch), MS).cpu().numpy()
+    torch.cuda.synchronize()
+    del H, grad
+    say("  oracle tensor")
+    Nfull = tensor_full(n, H_CELL)
+    say("  oracle convolution")
+    M = MS * m.astype(np.float64)
+    Hr = conv.fft_conv(M, H_CELL, Nfull)
+    Er = conv.energy(M, Hr, H_CELL)
+    gr = MS * conv.fft_conv(G.astype(np.float64), H_CELL, Nfull)
+    nx, ny, nz = n
+    octant = Nfull[:, nz - 1:, ny - 1:, nx - 1:]
+    rng = np.random.default_rng(seed)
+    targets = [(int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx))) for _ in range(6)]
+    targets += [(0, 0, 0), (nz - 1, ny - 1, nx - 1)]
+    say("  oracle direct sum at sampled cells")
+    Hs = conv.direct_sum_at(M, H_CELL, targets, octant)
+    for q, (tz, ty, tx) in enumerate(targets):
+        got = Hn[:, tz, ty, tx]
+        assert np.linalg.norm(got - Hs[q]) <= 1e-4 * np.linalg.norm(Hs[q]) + 1e-6 * np.linalg.norm(Hr) / np.sqrt(Hr[0].size)
+    del Nfull, octant
+    e1, e2, e3 = rel_l2(Hn, Hr), abs(En - Er) / Er, rel_l2(gn, gr)
+    say(f"  rel-L2 H {e1:.2e}  E {e2:.2e}  grad {e3:.2e}")
+    assert e1 < TOL and e2 < TOL and e3 < TOL
+    Nbox = np.array(aharoni_diag(nx * H_CELL[0], ny * H_CELL[1], nz * H_CELL[2]))
+    mean = Hu.mean(axis=(1, 2, 3)) / MS
+    want = -Nbox * u[:, 0, 0, 0]
+    say(f"  uniform box mean field {mean} vs {want}")
+    assert np.allclose(mean, want, rtol=2e-5, atol=2e-6)
