@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -60,10 +61,7 @@ int ilog2i(int n) {
   return l;
 }
 
-int line_threads(int M) {  // lanes per line of the x passes (matches LineShape)
-  const int R = M >= 1024 ? 16 : (M >= 8 ? 8 : M);
-  return M / R;
-}
+int line_threads(int M) { return M / line_radix(M); }  // lanes per line of the x passes
 
 // Gauss-Legendre rule of order n on [-1, 1] by Newton iteration on P_n.
 void gauss_legendre(int n, double* x, double* w) {
@@ -123,18 +121,21 @@ int demag_setup(demag_plan** out, int nx, int ny, int nz, double dx, double dy, 
   g.Kzh = g.Nz > 1 ? g.Nz / 2 + 1 : 1;
   g.nTiles = (g.Kx + TILE - 1) / TILE;
   g.dx = dx; g.dy = dy; g.dz = dz;
-  const size_t pitch_bytes = (size_t)((g.Nx >= 4 ? g.Nx / 2 : 1) + 1) * sizeof(float2);
-  if ((size_t)nz * pitch_bytes > 160 * 1024)
-    return fail(DEMAG_EUNSUPPORTED, "demag_setup: nz * (Nx/2 + 1) * 8 bytes must fit in 160 KiB of LDS");
+  const size_t pitch_bytes = (size_t)xrow_pitch_rt(g.lnx) * sizeof(float2);
+  const size_t tab_bytes = 8192;   // stage twiddle table of the x passes (upper bound)
+  if ((size_t)nz * pitch_bytes + tab_bytes > 160 * 1024)
+    return fail(DEMAG_EUNSUPPORTED, "demag_setup: the nz rows of one y line must fit in 160 KiB of LDS");
   // y rows per workgroup of the x passes: enough rows for one round of the
   // workgroup, within 64 KiB of LDS
   const int P = g.Nx >= 4 ? g.Nx / 4 : 1;
   const int rpr = FWD_THREADS / (2 * line_threads(P));
   int yg = (rpr + nz - 1) / nz;
-  while (yg > 1 && (size_t)yg * nz * pitch_bytes > 65536) --yg;
+  while (yg > 1 && (size_t)yg * nz * pitch_bytes + tab_bytes > 65536) --yg;
   if (yg > ny) yg = ny;
   if (yg < 1) yg = 1;
   g.yg = yg;
+  g.mid_kw = 4;
+  if (const char* kw = std::getenv("DEMAG_MID_KW")) g.mid_kw = std::atoi(kw) == 8 ? 8 : 4;
 
   demag_plan* p = new (std::nothrow) demag_plan;
   if (!p) return fail(DEMAG_ENOMEM, "demag_setup: out of host memory");

@@ -14,6 +14,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "plan.hpp"
+
 namespace demag {
 
 constexpr int TW_LOG2 = 12;
@@ -49,23 +51,26 @@ __device__ __forceinline__ float2 twiddle(const float2* __restrict__ tw, int m, 
   return w;
 }
 
-// Compile-time twiddles W_16^k for the in-register butterflies.
-__device__ __forceinline__ constexpr float c16(int k) {
-  return k == 0 ? 1.0f : k == 1 ? 0.92387953251128674f : k == 2 ? 0.70710678118654752f
-       : k == 3 ? 0.38268343236508977f : k == 4 ? 0.0f : k == 5 ? -0.38268343236508977f
-       : k == 6 ? -0.70710678118654752f : k == 7 ? -0.92387953251128674f : -1.0f;
+// Compile-time cos(2 pi k / 32), 0 <= k <= 16, for the in-register butterflies.
+__device__ __forceinline__ constexpr float cos32(int k) {
+  return k == 0 ? 1.0f : k == 1 ? 0.98078528040323043f : k == 2 ? 0.92387953251128674f
+       : k == 3 ? 0.83146961230254524f : k == 4 ? 0.70710678118654752f : k == 5 ? 0.55557023301960218f
+       : k == 6 ? 0.38268343236508977f : k == 7 ? 0.19509032201612826f : k == 8 ? 0.0f
+       : -cos32(16 - k);
 }
-// a * W_LEN^J (forward: exp(-2 pi i J/LEN); INV: conjugate), LEN <= 16, J < LEN/2.
+
+// a * W_LEN^J (forward: exp(-2 pi i J/LEN); INV: conjugate), LEN <= 32, J < LEN/2.
 template <int LEN, int J, bool INV>
 __device__ __forceinline__ float2 tw_const(float2 a) {
-  constexpr int k = J * (16 / LEN);  // index into W_16, 0 <= k < 8
+  static_assert(LEN <= 32 && J < LEN / 2, "constant twiddle out of range");
+  constexpr int k = J * (32 / LEN);  // angle 2 pi k / 32, 0 <= k < 16
   if constexpr (k == 0) {
     return a;
-  } else if constexpr (k == 4) {     // -i (forward) / +i (inverse)
+  } else if constexpr (k == 8) {     // -i (forward) / +i (inverse)
     return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
   } else {
-    constexpr float c = c16(k);
-    constexpr float s = (k < 4) ? c16(4 - k) : c16(k - 4);  // sin(2 pi k/16) for 0 < k < 8
+    constexpr float c = cos32(k);
+    constexpr float s = cos32(k < 8 ? 8 - k : k - 8);  // sin(2 pi k/32) > 0
     // forward multiplies by (c - i s), inverse by (c + i s)
     if constexpr (INV) return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
     else return make_float2(a.x * c + a.y * s, a.y * c - a.x * s);
@@ -121,10 +126,57 @@ __device__ __forceinline__ void dft(float2 (&a)[R]) {
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
 
+// LDS placement of point i of an M-point line: one pad point after every
+// 2^s points (s = 3 for radix 8, 5 for radix 16).  It spreads the strided
+// Stockham accesses over the LDS banks while keeping every address an affine
+// function of the lane, so paired ds_read2/ds_write2 offsets still apply.
+template <int M, int R>
+__device__ __forceinline__ int swz(int i) { return i + (i >> line_pad_shift(R)); }
+// LDS points a group needs for an M-point line with this padding.
+template <int M, int R>
+constexpr int lds_points() { return M + (M >> line_pad_shift(R)); }
+
+// Twiddles of the later Stockham stages of an M-point line, kept in LDS in
+// the order [stage][r - 1][k] (k = butterfly index mod NS), so that lanes with
+// consecutive k read consecutive entries.  Stage s with NS and radix RS holds
+// W_{NS RS}^(r k) for 1 <= r < RS and 0 <= k < NS.
+template <int M, int R>
+constexpr int stage_table_size() {
+  int n = 0, ns = R;
+  while (ns < M) {
+    const int left = M / ns, rs = left >= R ? R : left;
+    n += (rs - 1) * ns;
+    ns *= rs;
+  }
+  return n;
+}
+
+// Fill the table cooperatively from the FP32 W_4096 table (threads nth).
+template <int M, int R>
+__device__ __forceinline__ void fill_stage_table(float2* __restrict__ tab, const float2* __restrict__ tw, int tid,
+                                                 int nth) {
+  constexpr int N = stage_table_size<M, R>();
+  for (int e = tid; e < N; e += nth) {
+    int ns = R, off = 0, q = e;
+    while (true) {
+      const int left = M / ns, rs = left >= R ? R : left;
+      const int cnt = (rs - 1) * ns;
+      if (q < cnt) {
+        const int r = q / ns + 1, k = q % ns;
+        tab[off + q] = twiddle<false>(tw, r * k, ilog2(ns * rs));
+        break;
+      }
+      q -= cnt;
+      off += cnt;
+      ns *= rs;
+    }
+  }
+}
+
 // One Stockham stage (not the first): NS = product of earlier radices, RS = this radix.
-template <int M, int R, int NS, int RS, bool INV>
+template <int M, int R, int NS, int RS, bool INV, int OFF>
 __device__ __forceinline__ void stockham_stage(float2 (&v)[R], float2* __restrict__ lds, int t,
-                                               const float2* __restrict__ tw) {
+                                               const float2* __restrict__ tab) {
   constexpr int T = M / R;
   constexpr int NB = R / RS;        // butterflies per lane
   constexpr bool LAST = (NS * RS == M);
@@ -133,16 +185,17 @@ __device__ __forceinline__ void stockham_stage(float2 (&v)[R], float2* __restric
   for (int i = 0; i < NB; ++i) {
     const int b = t + T * i;
 #pragma unroll
-    for (int r = 0; r < RS; ++r) a[i][r] = lds[b + r * (M / RS)];
+    for (int r = 0; r < RS; ++r) a[i][r] = lds[swz<M, R>(b + r * (M / RS))];
   }
   wave_sync();
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int b = t + T * i;
-    const int k = b & (NS - 1);
+    const int k = (t + T * i) & (NS - 1);
 #pragma unroll
-    for (int r = 1; r < RS; ++r)
-      a[i][r] = cmul(a[i][r], twiddle<INV>(tw, r * k, ilog2(NS * RS)));
+    for (int r = 1; r < RS; ++r) {
+      const float2 wv = tab[OFF + (r - 1) * NS + k];
+      a[i][r] = INV ? cmulc(a[i][r], wv) : cmul(a[i][r], wv);
+    }
     dft<RS, INV>(a[i]);
   }
   if constexpr (LAST) {
@@ -157,29 +210,29 @@ __device__ __forceinline__ void stockham_stage(float2 (&v)[R], float2* __restric
       const int k = b & (NS - 1);
       const int base = (b / NS) * NS * RS + k;
 #pragma unroll
-      for (int r = 0; r < RS; ++r) lds[base + r * NS] = a[i][r];
+      for (int r = 0; r < RS; ++r) lds[swz<M, R>(base + r * NS)] = a[i][r];
     }
     wave_sync();
   }
 }
 
-template <int M, int R, int NS, bool INV>
+template <int M, int R, int NS, bool INV, int OFF>
 __device__ __forceinline__ void stockham_rest(float2 (&v)[R], float2* __restrict__ lds, int t,
-                                              const float2* __restrict__ tw) {
+                                              const float2* __restrict__ tab) {
   if constexpr (NS < M) {
     constexpr int left = M / NS;
     constexpr int RS = left >= R ? R : left;
-    stockham_stage<M, R, NS, RS, INV>(v, lds, t, tw);
-    stockham_rest<M, R, NS * RS, INV>(v, lds, t, tw);
+    stockham_stage<M, R, NS, RS, INV, OFF>(v, lds, t, tab);
+    stockham_rest<M, R, NS * RS, INV, OFF + (RS - 1) * NS>(v, lds, t, tab);
   }
 }
 
 // Group FFT of M points, lane t in [0, M/R) of its group, stride-T layout in
-// and out.  lds: M points of scratch owned by this group (unused when M == R).
-// Unnormalized in both directions.
+// and out.  lds: M points of scratch owned by this group (unused when M == R);
+// tab: the stage twiddle table in LDS.  Unnormalized in both directions.
 template <int M, int R, bool INV>
 __device__ __forceinline__ void group_fft(float2 (&v)[R], float2* __restrict__ lds, int t,
-                                          const float2* __restrict__ tw) {
+                                          const float2* __restrict__ tab) {
   static_assert(M % R == 0, "R must divide M");
   constexpr int T = M / R;
   static_assert(T <= 64 && (64 % T) == 0, "a group must fit in one wavefront");
@@ -187,16 +240,35 @@ __device__ __forceinline__ void group_fft(float2 (&v)[R], float2* __restrict__ l
   if constexpr (M > R) {
     // first stage output index b*R + r for butterfly b = t
 #pragma unroll
-    for (int r = 0; r < R; ++r) lds[t * R + r] = v[r];
+    for (int r = 0; r < R; ++r) lds[swz<M, R>(t * R + r)] = v[r];
     wave_sync();
-    stockham_rest<M, R, R, INV>(v, lds, t, tw);
+    stockham_rest<M, R, R, INV, 0>(v, lds, t, tab);
   }
+}
+
+// v[j] *= W_{2M}^(t + T j) for j < R (INV: conjugate), where T = M / R, on
+// lanes with `on` set; other lanes multiply by 1.  The factor is one table
+// value W_{2M}^t (base) times the compile-time W_{2R}^j, picked by a select
+// rather than a branch so that divergent lanes do not keep two copies.
+template <int R, int J, bool INV>
+__device__ __forceinline__ void residue_twiddle_j(float2 (&v)[R], float2 base, bool on) {
+  if constexpr (J < R) {
+    float2 f = tw_const<2 * R, J, false>(base);
+    f.x = on ? f.x : 1.0f;
+    f.y = on ? f.y : 0.0f;
+    v[J] = INV ? cmulc(v[J], f) : cmul(v[J], f);
+    residue_twiddle_j<R, J + 1, INV>(v, base, on);
+  }
+}
+template <int R, bool INV>
+__device__ __forceinline__ void residue_twiddle(float2 (&v)[R], float2 base, bool on) {
+  residue_twiddle_j<R, 0, INV>(v, base, on);
 }
 
 // Points per lane used for an M-point line.
 template <int M>
 struct LineShape {
-  static constexpr int R = M >= 1024 ? 16 : (M >= 8 ? 8 : M);
+  static constexpr int R = line_radix(M);
   static constexpr int T = M / R;
 };
 

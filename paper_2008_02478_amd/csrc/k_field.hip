@@ -20,23 +20,49 @@
 
 namespace demag {
 
+__device__ __forceinline__ int xcd_logical(int b, int nblk) {
+  // workgroups are handed to the 8 XCDs round-robin; give each XCD a
+  // contiguous range of logical work so neighbours share its L2
+  const int x = b & 7, idx = b >> 3;
+  const int per = nblk >> 3, rem = nblk & 7;
+  return x * per + min(x, rem) + idx;
+}
+
+// LDS points reserved for the stage twiddle table of an M-point line FFT
+// (rounded up to 32 points so that the data after it stays 256-byte aligned).
+template <int M>
+constexpr int tab_points() {
+  constexpr int R = LineShape<M>::R;
+  return (M > R) ? ((stage_table_size<M, R>() + 31) / 32) * 32 : 0;
+}
+template <int LNX>
+constexpr int xrow_pitch() { return xrow_pitch_rt(LNX); }
+template <int LNX>
+constexpr int xtab_points() {
+  return (LNX >= 2) ? tab_points<((1 << LNX) / 4 > 0 ? (1 << LNX) / 4 : 1)>() : 0;
+}
+
 // ---------------------------------------------------------------------------
 // forward: x real-to-complex + z
 // ---------------------------------------------------------------------------
 template <int LNX, int LNZ>
-__global__ void __launch_bounds__(FWD_THREADS) k_fwd_xz(FwdArgs a) {
+__global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8))) k_fwd_xz(FwdArgs a) {
   constexpr int NX = 1 << LNX;
   constexpr int NZ = 1 << LNZ;
-  extern __shared__ float2 smem[];
-  const int c = blockIdx.y;
-  const int y0 = blockIdx.x * a.yg;
+  extern __shared__ float2 smem_base[];
+  const int nyb = (a.ny + a.yg - 1) / a.yg;
+  const int lg = xcd_logical(blockIdx.x, gridDim.x);
+  const int c = lg / nyb;
+  const int y0 = (lg - c * nyb) * a.yg;
   const int yg = min(a.yg, a.ny - y0);
   const int nz = a.nz, nx = a.nx, ny = a.ny;
   const int rows = yg * nz;
   const int tid = threadIdx.x;
   constexpr int L = (NX >= 4) ? NX / 2 : 1;   // packed complex length
-  constexpr int PITCH = L + 1;                // kx slots per row in LDS
+  constexpr int PITCH = xrow_pitch<LNX>();    // LDS points per row
   const float* msrow = nullptr;
+  float2* const tab = smem_base;
+  float2* const smem = smem_base + xtab_points<LNX>();
 
   if constexpr (NX == 1) {
     for (int row = tid; row < rows; row += FWD_THREADS) {
@@ -53,6 +79,9 @@ __global__ void __launch_bounds__(FWD_THREADS) k_fwd_xz(FwdArgs a) {
     const int sub = tid / (2 * T);
     const int r = (tid / T) & 1;
     const int t = tid % T;
+    fill_stage_table<P, R>(tab, a.tw, tid, FWD_THREADS);
+    const float2 rbase = twiddle<false>(a.tw, t, ilog2(2 * P));
+    __syncthreads();
     for (int start = 0; start < rows; start += RPR) {
       const int row = start + sub;
       const bool act = row < rows;
@@ -65,16 +94,14 @@ __global__ void __launch_bounds__(FWD_THREADS) k_fwd_xz(FwdArgs a) {
         msrow = a.Ms ? a.Ms + off : nullptr;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-          const int mm = t + T * j;
-          const int xi = 2 * mm;
+          const int xi = 2 * (t + T * j);
           float v0 = 0.f, v1 = 0.f;
           if (xi < nx) v0 = src[xi] * (msrow ? msrow[xi] : a.ms);
           if (xi + 1 < nx) v1 = src[xi + 1] * (msrow ? msrow[xi + 1] : a.ms);
-          float2 val = make_float2(v0, v1);
-          if (r) val = cmul(val, twiddle<false>(a.tw, mm, LNX - 1));
-          u[j] = val;
+          u[j] = make_float2(v0, v1);
         }
-        group_fft<P, R, false>(u, rb + r * P, t, a.tw);
+        residue_twiddle<R, false>(u, rbase, r != 0);
+        group_fft<P, R, false>(u, rb + r * lds_points<P, R>(), t, tab);
       }
       __syncthreads();
       if (act) {
@@ -105,33 +132,59 @@ __global__ void __launch_bounds__(FWD_THREADS) k_fwd_xz(FwdArgs a) {
   }
   __syncthreads();
 
-  // z transform per (y, kx) and store of the spectrum
+  // z transform per (y, kx) and store of the spectrum.  The x spectra at
+  // kx = 0 and kx = L are real, so those two columns share one complex z
+  // transform (A + iB), separated afterwards by conjugate symmetry; the
+  // remaining L - 1 columns take one transform each: L items per y row.
   const int Kx = a.Kx;
-  const int items = yg * Kx;
+  const int ncol = (NX >= 4) ? L : 1;
+  const int items = yg * ncol;
+  const size_t kzstride = (size_t)a.nTiles * ny * TILE;
   for (int it = tid; it < items; it += FWD_THREADS) {
-    const int yl = it / Kx, kx = it - yl * Kx;
+    const int yl = it / ncol, kx = it - yl * ncol;
     const int y = y0 + yl;
     float2* dst = a.T + ((((size_t)c * NZ) * a.nTiles + kx / TILE) * ny + y) * TILE + (kx % TILE);
-    const size_t kzstride = (size_t)a.nTiles * ny * TILE;
+    const bool pack = (NX >= 4) && kx == 0;
+    float2* dstL = a.T + ((((size_t)c * NZ) * a.nTiles + L / TILE) * ny + y) * TILE + (L % TILE);
     if constexpr (NZ == 1) {
-      dst[0] = smem[(yl * nz) * PITCH + kx];
+      if (pack) {
+        dst[0] = smem[(yl * nz) * PITCH];
+        dstL[0] = smem[(yl * nz) * PITCH + L];
+      } else {
+        dst[0] = smem[(yl * nz) * PITCH + kx];
+      }
     } else {
       constexpr int Q = NZ / 2;
       float2 xz[Q];
 #pragma unroll
-      for (int z = 0; z < Q; ++z)
-        xz[z] = (z < nz) ? smem[(yl * nz + z) * PITCH + kx] : make_float2(0.f, 0.f);
-      float2 v[Q];
+      for (int z = 0; z < Q; ++z) {
+        float2 val = make_float2(0.f, 0.f);
+        if (z < nz) {
+          const float2* rowp = &smem[(yl * nz + z) * PITCH];
+          val = pack ? make_float2(rowp[0].x, rowp[L].x) : rowp[kx];
+        }
+        xz[z] = val;
+      }
 #pragma unroll
-      for (int z = 0; z < Q; ++z) v[z] = xz[z];
-      dft<Q, false>(v);
+      for (int rz = 0; rz < 2; ++rz) {
+        float2 v[Q];
 #pragma unroll
-      for (int k = 0; k < Q; ++k) dst[(size_t)(2 * k) * kzstride] = v[k];
+        for (int z = 0; z < Q; ++z) v[z] = rz ? cmul(xz[z], twiddle<false>(a.tw, z, LNZ)) : xz[z];
+        dft<Q, false>(v);
+        if (pack) {
+          // v[k] = Z(2k + rz); its conjugate partner Z(-(2k + rz)) is v[(Q - k - rz) mod Q]
 #pragma unroll
-      for (int z = 0; z < Q; ++z) v[z] = cmul(xz[z], twiddle<false>(a.tw, z, LNZ));
-      dft<Q, false>(v);
+          for (int k = 0; k < Q; ++k) {
+            const float2 zp = v[k];
+            const float2 zm = v[(Q - k - rz) & (Q - 1)];
+            dst[(size_t)(2 * k + rz) * kzstride] = make_float2(0.5f * (zp.x + zm.x), 0.5f * (zp.y - zm.y));
+            dstL[(size_t)(2 * k + rz) * kzstride] = make_float2(0.5f * (zp.y + zm.y), -0.5f * (zp.x - zm.x));
+          }
+        } else {
 #pragma unroll
-      for (int k = 0; k < Q; ++k) dst[(size_t)(2 * k + 1) * kzstride] = v[k];
+          for (int k = 0; k < Q; ++k) dst[(size_t)(2 * k + rz) * kzstride] = v[k];
+        }
+      }
     }
   }
 }
@@ -139,13 +192,6 @@ __global__ void __launch_bounds__(FWD_THREADS) k_fwd_xz(FwdArgs a) {
 // ---------------------------------------------------------------------------
 // middle: y FFT, kernel product, inverse y FFT
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int xcd_logical(int b, int nblk) {
-  // workgroups are handed to the 8 XCDs round-robin; give each XCD a
-  // contiguous range of logical work so neighbours share its L2
-  const int x = b & 7, idx = b >> 3;
-  const int per = nblk >> 3, rem = nblk & 7;
-  return x * per + min(x, rem) + idx;
-}
 
 __device__ __forceinline__ int kz_of(int i, int Nz) {
   // 0, Nz/2, 1, Nz-1, 2, Nz-2, ...: +-kz share kernel lines
@@ -180,7 +226,7 @@ __device__ __forceinline__ Tv block_sum(Tv v, Tv* red) {
 }
 
 template <int LNY, int KW>
-__global__ void __launch_bounds__(mid_threads(LNY, KW))
+__global__ void __launch_bounds__(mid_threads(LNY, KW)) __attribute__((amdgpu_waves_per_eu(LNY >= 11 ? 2 : 4, 8)))
 k_mid(MidArgs a) {
   constexpr int NY = 1 << LNY;
   constexpr int M = NY > 1 ? NY / 2 : 1;
@@ -190,7 +236,9 @@ k_mid(MidArgs a) {
   constexpr int JOBS = NRES * KW;
   constexpr int NT = JOBS * T;
   __shared__ double red[16];
-  extern __shared__ float2 smem[];
+  extern __shared__ float2 smem_base[];
+  float2* const tab = smem_base;
+  float2* const smem = smem_base + tab_points<M>();
 
   const int nblk = gridDim.x;
   const int lg = xcd_logical(blockIdx.x, nblk);
@@ -203,15 +251,22 @@ k_mid(MidArgs a) {
 
   const int tid = threadIdx.x;
   const bool lane_act = tid < NT;
-  const int job = tid / T, t = tid % T;
+  const int job = (T == 64) ? __builtin_amdgcn_readfirstlane(tid / T) : tid / T;
+  const int t = tid % T;
   const int w = job / NRES, r = job % NRES;
   const int kx = tile * TILE + half * KW + w;
   const bool valid = lane_act && kx < a.Kx;
+  if (tile * TILE + half * KW >= a.Kx) {    // nothing but padding columns
+    if (a.epart && tid == 0) a.epart[lg] = 0.0;
+    return;
+  }
   float2* stage = smem;                     // ny * KW points
-  float2* scr = smem + (size_t)job * M;     // M points per job (aliases stage)
+  float2* scr = smem + (size_t)job * lds_points<M, R>();   // per-job scratch (aliases stage)
   const size_t cstride = (size_t)a.Nz * a.nTiles * ny * TILE;
   float2* blk0 = a.T + ((size_t)kz * a.nTiles + tile) * ny * TILE + half * KW;
 
+  if constexpr (M > R) fill_stage_table<M, R>(tab, a.tw, tid, blockDim.x);
+  const float2 rbase = twiddle<false>(a.tw, t, ilog2(2 * M));
   float2 v[3][R];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -225,15 +280,14 @@ k_mid(MidArgs a) {
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       const int y = t + T * j;
-      float2 val = (valid && y < ny) ? stage[y * KW + w] : make_float2(0.f, 0.f);
-      if (NRES == 2 && r) val = cmul(val, twiddle<false>(a.tw, y, LNY));
-      v[c][j] = val;
+      v[c][j] = (valid && y < ny) ? stage[y * KW + w] : make_float2(0.f, 0.f);
     }
+    if constexpr (NRES == 2) residue_twiddle<R, false>(v[c], rbase, r != 0);
   }
   __syncthreads();
   if (lane_act) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) group_fft<M, R, false>(v[c], scr, t, a.tw);
+    for (int c = 0; c < 3; ++c) group_fft<M, R, false>(v[c], scr, t, tab);
   }
 
   // point-wise product with the real, symmetric kernel spectrum
@@ -244,6 +298,7 @@ k_mid(MidArgs a) {
     const int kxc = min(kx, a.Kx - 1);
     const float* Kb = a.K + ((size_t)kzf * a.Kx + kxc) * 6 * a.Kyh;
     const float wkx = (kx == 0 || 2 * kx == a.Nx) ? 1.f : 2.f;
+    float ef = 0.f;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       const int ky = NRES * (t + T * j) + r;
@@ -260,19 +315,14 @@ k_mid(MidArgs a) {
       const float2 hx = make_float2(kxx * mx.x + kxy * my.x + kxz * mz.x, kxx * mx.y + kxy * my.y + kxz * mz.y);
       const float2 hy = make_float2(kxy * mx.x + kyy * my.x + kyz * mz.x, kxy * mx.y + kyy * my.y + kyz * mz.y);
       const float2 hz = make_float2(kxz * mx.x + kyz * my.x + kzz * mz.x, kxz * mx.y + kyz * my.y + kzz * mz.y);
-      if (a.epart && valid) {
-        const float d = mx.x * hx.x + mx.y * hx.y + my.x * hy.x + my.y * hy.y + mz.x * hz.x + mz.y * hz.y;
-        e += (double)(wkx * d);
-      }
+      ef += mx.x * hx.x + mx.y * hx.y + my.x * hy.x + my.y * hy.y + mz.x * hz.x + mz.y * hz.y;
       v[0][j] = hx; v[1][j] = hy; v[2][j] = hz;
     }
+    if (a.epart && valid) e = (double)(wkx * ef);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      group_fft<M, R, true>(v[c], scr, t, a.tw);
-      if (NRES == 2 && r) {
-#pragma unroll
-        for (int j = 0; j < R; ++j) v[c][j] = cmul(v[c][j], twiddle<true>(a.tw, t + T * j, LNY));
-      }
+      group_fft<M, R, true>(v[c], scr, t, tab);
+      if constexpr (NRES == 2) residue_twiddle<R, true>(v[c], rbase, r != 0);
     }
   }
 
@@ -314,43 +364,75 @@ k_mid(MidArgs a) {
 // inverse: z + x complex-to-real
 // ---------------------------------------------------------------------------
 template <int LNX, int LNZ>
-__global__ void __launch_bounds__(INV_THREADS) k_inv_zx(InvArgs a) {
+__global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8))) k_inv_zx(InvArgs a) {
   constexpr int NX = 1 << LNX;
   constexpr int NZ = 1 << LNZ;
-  extern __shared__ float2 smem[];
-  const int c = blockIdx.y;
-  const int y0 = blockIdx.x * a.yg;
+  extern __shared__ float2 smem_base[];
+  const int nyb = (a.ny + a.yg - 1) / a.yg;
+  const int lg = xcd_logical(blockIdx.x, gridDim.x);
+  const int c = lg / nyb;
+  const int y0 = (lg - c * nyb) * a.yg;
   const int yg = min(a.yg, a.ny - y0);
   const int nz = a.nz, nx = a.nx, ny = a.ny;
   const int rows = yg * nz;
   const int tid = threadIdx.x;
   constexpr int L = (NX >= 4) ? NX / 2 : 1;
-  constexpr int PITCH = L + 1;
+  constexpr int PITCH = xrow_pitch<LNX>();
   const int Kx = a.Kx;
+  float2* const tab = smem_base;
+  float2* const smem = smem_base + xtab_points<LNX>();
 
-  // inverse z per (y, kx), keeping z < nz
-  const int items = yg * Kx;
+  // inverse z per (y, kx), keeping z < nz.  Columns kx = 0 and kx = L hold
+  // spectra of real z lines, so one complex inverse of A + iB returns both
+  // (real and imaginary parts): L items per y row.
+  const int ncol = (NX >= 4) ? L : 1;
+  const int items = yg * ncol;
+  const size_t kzstride = (size_t)a.nTiles * ny * TILE;
   for (int it = tid; it < items; it += INV_THREADS) {
-    const int yl = it / Kx, kx = it - yl * Kx;
+    const int yl = it / ncol, kx = it - yl * ncol;
     const int y = y0 + yl;
     const float2* src = a.T + ((((size_t)c * NZ) * a.nTiles + kx / TILE) * ny + y) * TILE + (kx % TILE);
-    const size_t kzstride = (size_t)a.nTiles * ny * TILE;
+    const bool pack = (NX >= 4) && kx == 0;
+    const float2* srcL = a.T + ((((size_t)c * NZ) * a.nTiles + L / TILE) * ny + y) * TILE + (L % TILE);
     if constexpr (NZ == 1) {
-      smem[(yl * nz) * PITCH + kx] = src[0];
-    } else {
-      constexpr int Q = NZ / 2;
-      float2 ve[Q], vo[Q];
-#pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        ve[k] = src[(size_t)(2 * k) * kzstride];
-        vo[k] = src[(size_t)(2 * k + 1) * kzstride];
+      if (pack) {
+        smem[(yl * nz) * PITCH] = make_float2(src[0].x, 0.f);
+        smem[(yl * nz) * PITCH + L] = make_float2(srcL[0].x, 0.f);
+      } else {
+        smem[(yl * nz) * PITCH + kx] = src[0];
       }
-      dft<Q, true>(ve);
-      dft<Q, true>(vo);
+    } else {
+      // even kz residue, then the odd one added through LDS (keeps one
+      // residue live at a time)
+      constexpr int Q = NZ / 2;
+      float2 v[Q];
 #pragma unroll
-      for (int z = 0; z < Q; ++z) {
-        if (z < nz)
-          smem[(yl * nz + z) * PITCH + kx] = cadd(ve[z], cmul(vo[z], twiddle<true>(a.tw, z, LNZ)));
+      for (int rz = 0; rz < 2; ++rz) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          const size_t o = (size_t)(2 * k + rz) * kzstride;
+          if (pack) {
+            const float2 A = src[o], B = srcL[o];
+            v[k] = make_float2(A.x - B.y, A.y + B.x);
+          } else {
+            v[k] = src[o];
+          }
+        }
+        dft<Q, true>(v);
+#pragma unroll
+        for (int z = 0; z < Q; ++z) {
+          if (z < nz) {
+            float2* d = &smem[(yl * nz + z) * PITCH + kx];
+            const float2 w = rz ? cmul(v[z], twiddle<true>(a.tw, z, LNZ)) : v[z];
+            const float2 h = rz ? cadd(*d, w) : w;
+            if (pack && rz) {
+              d[0] = make_float2(h.x, 0.f);
+              d[L] = make_float2(h.y, 0.f);
+            } else {
+              *d = h;
+            }
+          }
+        }
       }
     }
   }
@@ -377,6 +459,9 @@ __global__ void __launch_bounds__(INV_THREADS) k_inv_zx(InvArgs a) {
     const int sub = tid / (2 * T);
     const int r = (tid / T) & 1;
     const int t = tid % T;
+    fill_stage_table<P, R>(tab, a.tw, tid, INV_THREADS);
+    const float2 rbase = twiddle<false>(a.tw, t, ilog2(2 * P));
+    __syncthreads();
     const float beta = (a.scale_out && a.beta_ptr) ? (float)(a.beta_scale * *a.beta_ptr) : 0.f;
     for (int start = 0; start < rows; start += RPR) {
       const int row = start + sub;
@@ -399,11 +484,8 @@ __global__ void __launch_bounds__(INV_THREADS) k_inv_zx(InvArgs a) {
       }
       __syncthreads();
       if (act) {
-        group_fft<P, R, true>(u, rb + r * P, t, a.tw);
-        if (r) {
-#pragma unroll
-          for (int j = 0; j < R; ++j) u[j] = cmul(u[j], twiddle<true>(a.tw, t + T * j, LNX - 1));
-        }
+        group_fft<P, R, true>(u, rb + r * lds_points<P, R>(), t, tab);
+        residue_twiddle<R, true>(u, rbase, r != 0);
       }
       __syncthreads();
       if (act && r == 1) {
@@ -474,8 +556,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_energy_cells(const float* m, co
 namespace demag {
 
 static size_t xpass_lds(const Geom& g) {
-  const int pitch = (g.Nx >= 4 ? g.Nx / 2 : 1) + 1;
-  return (size_t)g.yg * g.nz * pitch * sizeof(float2);
+  return (size_t)g.yg * g.nz * xrow_pitch_rt(g.lnx) * sizeof(float2);
 }
 
 template <typename K>
@@ -487,20 +568,20 @@ static hipError_t prep_lds(K kern, size_t lds) {
 
 template <int LNX, int LNZ>
 static hipError_t fwd_one(const Geom& g, const FwdArgs& a, hipStream_t s) {
-  const size_t lds = xpass_lds(g);
+  const size_t lds = xpass_lds(g) + xtab_points<LNX>() * sizeof(float2);
   hipError_t e = prep_lds(k_fwd_xz<LNX, LNZ>, lds);
   if (e != hipSuccess) return e;
-  dim3 grid((g.ny + g.yg - 1) / g.yg, 3);
+  dim3 grid(((g.ny + g.yg - 1) / g.yg) * 3);
   hipLaunchKernelGGL((k_fwd_xz<LNX, LNZ>), grid, dim3(FWD_THREADS), lds, s, a);
   return hipGetLastError();
 }
 
 template <int LNX, int LNZ>
 static hipError_t inv_one(const Geom& g, const InvArgs& a, hipStream_t s) {
-  const size_t lds = xpass_lds(g);
+  const size_t lds = xpass_lds(g) + xtab_points<LNX>() * sizeof(float2);
   hipError_t e = prep_lds(k_inv_zx<LNX, LNZ>, lds);
   if (e != hipSuccess) return e;
-  dim3 grid((g.ny + g.yg - 1) / g.yg, 3);
+  dim3 grid(((g.ny + g.yg - 1) / g.yg) * 3);
   hipLaunchKernelGGL((k_inv_zx<LNX, LNZ>), grid, dim3(INV_THREADS), lds, s, a);
   return hipGetLastError();
 }
@@ -541,8 +622,8 @@ hipError_t launch_fwd(const Geom& g, const FwdArgs& a, hipStream_t s) { DEMAG_X_
 hipError_t launch_inv(const Geom& g, const InvArgs& a, hipStream_t s) { DEMAG_X_SWITCH(inv_z, g, a, s) }
 
 int mid_kw(const Geom& g) {
-  const int M = g.Ny > 1 ? g.Ny / 2 : 1;
-  return (2 * 8 * (size_t)M * sizeof(float2) <= 65536) ? 8 : 4;
+  if (g.mid_kw == 4 || g.mid_kw == 8) return g.mid_kw;
+  return 4;
 }
 
 int mid_blocks(const Geom& g) { return g.nTiles * (TILE / mid_kw(g)) * g.Nz; }
@@ -552,9 +633,10 @@ static hipError_t mid_one(const Geom& g, const MidArgs& a, hipStream_t s) {
   constexpr int NY = 1 << LNY;
   constexpr int M = NY > 1 ? NY / 2 : 1;
   constexpr int NRES = NY > 1 ? 2 : 1;
-  size_t lds = (size_t)NRES * KW * M * sizeof(float2);
+  size_t lds = (size_t)NRES * KW * lds_points<M, LineShape<M>::R>() * sizeof(float2);
   const size_t st = (size_t)g.ny * KW * sizeof(float2);
   if (st > lds) lds = st;
+  lds += tab_points<M>() * sizeof(float2);
   hipError_t e = prep_lds(k_mid<LNY, KW>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_mid<LNY, KW>), dim3(mid_blocks(g)), dim3(mid_threads(LNY, KW)), lds, s, a);

@@ -7,9 +7,25 @@
 namespace demag {
 
 constexpr int TILE = 8;          // kx points per tile of the spectrum work buffer
-constexpr int FWD_THREADS = 256;
-constexpr int INV_THREADS = 256;
+constexpr int FWD_THREADS = 512;
+constexpr int INV_THREADS = 512;
 constexpr int RED_THREADS = 256;
+
+// Points per lane (R) of an M-point line FFT, and its padded LDS footprint
+// (one pad point after every 2^3 points for radix 8, 2^5 for radix 16).
+constexpr int line_radix(int M) { return M >= 1024 ? 16 : (M >= 8 ? 8 : M); }
+constexpr int line_pad_shift(int R) { return R >= 16 ? 5 : 3; }
+constexpr int line_lds_points(int M) { return M + (M >> line_pad_shift(line_radix(M))); }
+
+// LDS points per row of the x passes for Nx = 2^lnx: the half spectrum
+// (Nx/2 + 1 points) and, while the row is transformed, the padded scratch of
+// its two Nx/4-point residue FFTs.
+constexpr int xrow_pitch_rt(int lnx) {
+  if (lnx < 2) return 2;
+  const int L = (1 << lnx) / 2, P = L / 2;
+  const int sc = 2 * line_lds_points(P);
+  return sc > L + 1 ? sc : L + 1;
+}
 
 // Sizes of one mesh.  Padded lengths are powers of two >= 2n-1 (1 for n == 1).
 struct Geom {
@@ -20,6 +36,7 @@ struct Geom {
   int Kyh, Kzh;        // Ny/2 + 1, Nz/2 + 1 (1 for unit lengths): stored octant
   int nTiles;          // ceil(Kx / TILE)
   int yg;              // y rows per workgroup in the x passes
+  int mid_kw;          // kx lines per workgroup of the middle pass (4 or 8)
   double dx, dy, dz;
 };
 

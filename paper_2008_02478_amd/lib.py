@@ -4,7 +4,7 @@ computation runs in the library's HIP kernels."""
 import ctypes
 import os
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdemag.so")
+LIB_PATH = os.environ.get("DEMAG_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdemag.so")
 
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
 PBC_X, PBC_Y, PBC_Z = 1, 2, 4
