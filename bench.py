@@ -137,6 +137,14 @@ def main():
     pass_us = {k: 1e3 * float(np.mean(v)) for k, v in passes.items()}
     mid_bytes = mid_pass_bytes(n)
     achieved = mid_bytes / (pass_us["mid_y"] * 1e-6) / 1e9
+    traffic = None
+    side = os.path.join(ROOT, "profiles", f"k_mid_{args.workload}.json")
+    if os.path.exists(side):
+        from paper_2008_02478_amd.profiling import source_hash
+        with open(side) as f:
+            prof = json.load(f)
+        if prof.get("source_hash") == source_hash():   # counters of this very kernel build
+            traffic = prof["traffic_bytes"]
 
     out = {
         "metric": "demag field evals/sec and cell-updates/s (fwd+bwd) at 512x512x16 FP32; HBM GB/s",
@@ -166,7 +174,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "algorithmic_bytes_per_launch": mid_bytes,
         },
     }

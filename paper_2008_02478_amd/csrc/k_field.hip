@@ -132,58 +132,30 @@ __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_e
   }
   __syncthreads();
 
-  // z transform per (y, kx) and store of the spectrum.  The x spectra at
-  // kx = 0 and kx = L are real, so those two columns share one complex z
-  // transform (A + iB), separated afterwards by conjugate symmetry; the
-  // remaining L - 1 columns take one transform each: L items per y row.
+  // z transform per (y, kx) and store of the spectrum
   const int Kx = a.Kx;
-  const int ncol = (NX >= 4) ? L : 1;
-  const int items = yg * ncol;
+  const int items = yg * Kx;
   const size_t kzstride = (size_t)a.nTiles * ny * TILE;
   for (int it = tid; it < items; it += FWD_THREADS) {
-    const int yl = it / ncol, kx = it - yl * ncol;
+    const int yl = it / Kx, kx = it - yl * Kx;
     const int y = y0 + yl;
     float2* dst = a.T + ((((size_t)c * NZ) * a.nTiles + kx / TILE) * ny + y) * TILE + (kx % TILE);
-    const bool pack = (NX >= 4) && kx == 0;
-    float2* dstL = a.T + ((((size_t)c * NZ) * a.nTiles + L / TILE) * ny + y) * TILE + (L % TILE);
     if constexpr (NZ == 1) {
-      if (pack) {
-        dst[0] = smem[(yl * nz) * PITCH];
-        dstL[0] = smem[(yl * nz) * PITCH + L];
-      } else {
-        dst[0] = smem[(yl * nz) * PITCH + kx];
-      }
+      dst[0] = smem[(yl * nz) * PITCH + kx];
     } else {
       constexpr int Q = NZ / 2;
       float2 xz[Q];
 #pragma unroll
-      for (int z = 0; z < Q; ++z) {
-        float2 val = make_float2(0.f, 0.f);
-        if (z < nz) {
-          const float2* rowp = &smem[(yl * nz + z) * PITCH];
-          val = pack ? make_float2(rowp[0].x, rowp[L].x) : rowp[kx];
-        }
-        xz[z] = val;
-      }
+      for (int z = 0; z < Q; ++z)
+        xz[z] = (z < nz) ? smem[(yl * nz + z) * PITCH + kx] : make_float2(0.f, 0.f);
 #pragma unroll
       for (int rz = 0; rz < 2; ++rz) {
         float2 v[Q];
 #pragma unroll
         for (int z = 0; z < Q; ++z) v[z] = rz ? cmul(xz[z], twiddle<false>(a.tw, z, LNZ)) : xz[z];
         dft<Q, false>(v);
-        if (pack) {
-          // v[k] = Z(2k + rz); its conjugate partner Z(-(2k + rz)) is v[(Q - k - rz) mod Q]
 #pragma unroll
-          for (int k = 0; k < Q; ++k) {
-            const float2 zp = v[k];
-            const float2 zm = v[(Q - k - rz) & (Q - 1)];
-            dst[(size_t)(2 * k + rz) * kzstride] = make_float2(0.5f * (zp.x + zm.x), 0.5f * (zp.y - zm.y));
-            dstL[(size_t)(2 * k + rz) * kzstride] = make_float2(0.5f * (zp.y + zm.y), -0.5f * (zp.x - zm.x));
-          }
-        } else {
-#pragma unroll
-          for (int k = 0; k < Q; ++k) dst[(size_t)(2 * k + rz) * kzstride] = v[k];
-        }
+        for (int k = 0; k < Q; ++k) dst[(size_t)(2 * k + rz) * kzstride] = v[k];
       }
     }
   }
@@ -382,55 +354,29 @@ __global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_e
   float2* const tab = smem_base;
   float2* const smem = smem_base + xtab_points<LNX>();
 
-  // inverse z per (y, kx), keeping z < nz.  Columns kx = 0 and kx = L hold
-  // spectra of real z lines, so one complex inverse of A + iB returns both
-  // (real and imaginary parts): L items per y row.
-  const int ncol = (NX >= 4) ? L : 1;
-  const int items = yg * ncol;
+  // inverse z per (y, kx), keeping z < nz: the even kz residue, then the
+  // odd one added through LDS (one residue live at a time)
+  const int items = yg * Kx;
   const size_t kzstride = (size_t)a.nTiles * ny * TILE;
   for (int it = tid; it < items; it += INV_THREADS) {
-    const int yl = it / ncol, kx = it - yl * ncol;
+    const int yl = it / Kx, kx = it - yl * Kx;
     const int y = y0 + yl;
     const float2* src = a.T + ((((size_t)c * NZ) * a.nTiles + kx / TILE) * ny + y) * TILE + (kx % TILE);
-    const bool pack = (NX >= 4) && kx == 0;
-    const float2* srcL = a.T + ((((size_t)c * NZ) * a.nTiles + L / TILE) * ny + y) * TILE + (L % TILE);
     if constexpr (NZ == 1) {
-      if (pack) {
-        smem[(yl * nz) * PITCH] = make_float2(src[0].x, 0.f);
-        smem[(yl * nz) * PITCH + L] = make_float2(srcL[0].x, 0.f);
-      } else {
-        smem[(yl * nz) * PITCH + kx] = src[0];
-      }
+      smem[(yl * nz) * PITCH + kx] = src[0];
     } else {
-      // even kz residue, then the odd one added through LDS (keeps one
-      // residue live at a time)
       constexpr int Q = NZ / 2;
       float2 v[Q];
 #pragma unroll
       for (int rz = 0; rz < 2; ++rz) {
 #pragma unroll
-        for (int k = 0; k < Q; ++k) {
-          const size_t o = (size_t)(2 * k + rz) * kzstride;
-          if (pack) {
-            const float2 A = src[o], B = srcL[o];
-            v[k] = make_float2(A.x - B.y, A.y + B.x);
-          } else {
-            v[k] = src[o];
-          }
-        }
+        for (int k = 0; k < Q; ++k) v[k] = src[(size_t)(2 * k + rz) * kzstride];
         dft<Q, true>(v);
 #pragma unroll
         for (int z = 0; z < Q; ++z) {
           if (z < nz) {
             float2* d = &smem[(yl * nz + z) * PITCH + kx];
-            const float2 w = rz ? cmul(v[z], twiddle<true>(a.tw, z, LNZ)) : v[z];
-            const float2 h = rz ? cadd(*d, w) : w;
-            if (pack && rz) {
-              d[0] = make_float2(h.x, 0.f);
-              d[L] = make_float2(h.y, 0.f);
-            } else {
-              *d = h;
-            }
+            *d = rz ? cadd(*d, cmul(v[z], twiddle<true>(a.tw, z, LNZ))) : v[z];
           }
         }
       }
