@@ -135,7 +135,10 @@ int demag_setup(demag_plan** out, int nx, int ny, int nz, double dx, double dy, 
   if (yg < 1) yg = 1;
   g.yg = yg;
   g.mid_kw = 4;
-  if (const char* kw = std::getenv("DEMAG_MID_KW")) g.mid_kw = std::atoi(kw) == 8 ? 8 : 4;
+  if (const char* kw = std::getenv("DEMAG_MID_KW")) {
+    const int v = std::atoi(kw);
+    g.mid_kw = (v == 2 || v == 8) ? v : 4;
+  }
 
   demag_plan* p = new (std::nothrow) demag_plan;
   if (!p) return fail(DEMAG_ENOMEM, "demag_setup: out of host memory");

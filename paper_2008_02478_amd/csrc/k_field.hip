@@ -28,6 +28,15 @@ __device__ __forceinline__ int xcd_logical(int b, int nblk) {
   return x * per + min(x, rem) + idx;
 }
 
+// v[z] *= W_NZ^z (forward) or its conjugate, z < NZ/2, as compile-time constants.
+template <int NZ, int Z, bool INV>
+__device__ __forceinline__ void zodd_twiddle(float2 (&v)[NZ / 2]) {
+  if constexpr (Z < NZ / 2) {
+    v[Z] = tw_const<NZ, Z, INV>(v[Z]);
+    zodd_twiddle<NZ, Z + 1, INV>(v);
+  }
+}
+
 // LDS points reserved for the stage twiddle table of an M-point line FFT
 // (rounded up to 32 points so that the data after it stays 256-byte aligned).
 template <int M>
@@ -92,13 +101,34 @@ __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_e
         const size_t off = ((size_t)z * ny + (y0 + yl)) * nx;
         const float* src = a.m + (size_t)c * nz * ny * nx + off;
         msrow = a.Ms ? a.Ms + off : nullptr;
+        if ((nx & 1) == 0) {
+          // even rows: (x[2m], x[2m+1]) is one aligned float2
+          const float2* s2 = reinterpret_cast<const float2*>(src);
+          const float2* m2 = reinterpret_cast<const float2*>(msrow);
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-          const int xi = 2 * (t + T * j);
-          float v0 = 0.f, v1 = 0.f;
-          if (xi < nx) v0 = src[xi] * (msrow ? msrow[xi] : a.ms);
-          if (xi + 1 < nx) v1 = src[xi + 1] * (msrow ? msrow[xi + 1] : a.ms);
-          u[j] = make_float2(v0, v1);
+          for (int j = 0; j < R; ++j) {
+            const int mm = t + T * j;
+            float2 val = make_float2(0.f, 0.f);
+            if (2 * mm < nx) {
+              val = s2[mm];
+              if (m2) {
+                const float2 ms2 = m2[mm];
+                val = make_float2(val.x * ms2.x, val.y * ms2.y);
+              } else {
+                val = make_float2(val.x * a.ms, val.y * a.ms);
+              }
+            }
+            u[j] = val;
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < R; ++j) {
+            const int xi = 2 * (t + T * j);
+            float v0 = 0.f, v1 = 0.f;
+            if (xi < nx) v0 = src[xi] * (msrow ? msrow[xi] : a.ms);
+            if (xi + 1 < nx) v1 = src[xi + 1] * (msrow ? msrow[xi + 1] : a.ms);
+            u[j] = make_float2(v0, v1);
+          }
         }
         residue_twiddle<R, false>(u, rbase, r != 0);
         group_fft<P, R, false>(u, rb + r * lds_points<P, R>(), t, tab);
@@ -135,28 +165,29 @@ __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_e
   // z transform per (y, kx) and store of the spectrum
   const int Kx = a.Kx;
   const int items = yg * Kx;
-  const size_t kzstride = (size_t)a.nTiles * ny * TILE;
+  const unsigned kzstride = (unsigned)a.nTiles * ny * TILE;   // float2 elements
+  float2* const Tc = a.T + (size_t)c * NZ * kzstride;
   for (int it = tid; it < items; it += FWD_THREADS) {
     const int yl = it / Kx, kx = it - yl * Kx;
-    const int y = y0 + yl;
-    float2* dst = a.T + ((((size_t)c * NZ) * a.nTiles + kx / TILE) * ny + y) * TILE + (kx % TILE);
+    const unsigned o = ((unsigned)(kx / TILE) * ny + (y0 + yl)) * TILE + (kx % TILE);
     if constexpr (NZ == 1) {
-      dst[0] = smem[(yl * nz) * PITCH + kx];
+      Tc[o] = smem[(yl * nz) * PITCH + kx];
     } else {
       constexpr int Q = NZ / 2;
       float2 xz[Q];
 #pragma unroll
       for (int z = 0; z < Q; ++z)
         xz[z] = (z < nz) ? smem[(yl * nz + z) * PITCH + kx] : make_float2(0.f, 0.f);
+      float2 v[Q];
 #pragma unroll
-      for (int rz = 0; rz < 2; ++rz) {
-        float2 v[Q];
+      for (int z = 0; z < Q; ++z) v[z] = xz[z];
+      dft<Q, false>(v);
 #pragma unroll
-        for (int z = 0; z < Q; ++z) v[z] = rz ? cmul(xz[z], twiddle<false>(a.tw, z, LNZ)) : xz[z];
-        dft<Q, false>(v);
+      for (int k = 0; k < Q; ++k) Tc[o + (unsigned)(2 * k) * kzstride] = v[k];
+      zodd_twiddle<NZ, 0, false>(xz);
+      dft<Q, false>(xz);
 #pragma unroll
-        for (int k = 0; k < Q; ++k) dst[(size_t)(2 * k + rz) * kzstride] = v[k];
-      }
+      for (int k = 0; k < Q; ++k) Tc[o + (unsigned)(2 * k + 1) * kzstride] = xz[k];
     }
   }
 }
@@ -197,7 +228,7 @@ __device__ __forceinline__ Tv block_sum(Tv v, Tv* red) {
   return s;
 }
 
-template <int LNY, int KW>
+template <int LNY, int KW, bool ENERGY>
 __global__ void __launch_bounds__(mid_threads(LNY, KW)) __attribute__((amdgpu_waves_per_eu(LNY >= 11 ? 2 : 4, 8)))
 k_mid(MidArgs a) {
   constexpr int NY = 1 << LNY;
@@ -229,7 +260,7 @@ k_mid(MidArgs a) {
   const int kx = tile * TILE + half * KW + w;
   const bool valid = lane_act && kx < a.Kx;
   if (tile * TILE + half * KW >= a.Kx) {    // nothing but padding columns
-    if (a.epart && tid == 0) a.epart[lg] = 0.0;
+    if (ENERGY && tid == 0) a.epart[lg] = 0.0;
     return;
   }
   float2* stage = smem;                     // ny * KW points
@@ -244,9 +275,15 @@ k_mid(MidArgs a) {
   for (int c = 0; c < 3; ++c) {
     float2* blk = blk0 + c * cstride;
     __syncthreads();
-    for (int e = tid; e < ny * KW; e += blockDim.x) {
-      const int y = e / KW, q = e - y * KW;
-      stage[e] = blk[(size_t)y * TILE + q];
+    {
+      // 16-byte copies: KW/2 float4 per y row of the half tile
+      constexpr int V = KW / 2;
+      float4* st4 = reinterpret_cast<float4*>(stage);
+      const float4* b4 = reinterpret_cast<const float4*>(blk);
+      for (int e = tid; e < ny * V; e += blockDim.x) {
+        const int y = e / V, q = e - y * V;
+        st4[e] = b4[(unsigned)y * (TILE / 2) + q];
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -287,10 +324,11 @@ k_mid(MidArgs a) {
       const float2 hx = make_float2(kxx * mx.x + kxy * my.x + kxz * mz.x, kxx * mx.y + kxy * my.y + kxz * mz.y);
       const float2 hy = make_float2(kxy * mx.x + kyy * my.x + kyz * mz.x, kxy * mx.y + kyy * my.y + kyz * mz.y);
       const float2 hz = make_float2(kxz * mx.x + kyz * my.x + kzz * mz.x, kxz * mx.y + kyz * my.y + kzz * mz.y);
-      ef += mx.x * hx.x + mx.y * hx.y + my.x * hy.x + my.y * hy.y + mz.x * hz.x + mz.y * hz.y;
+      if constexpr (ENERGY)
+        ef += mx.x * hx.x + mx.y * hx.y + my.x * hy.x + my.y * hy.y + mz.x * hz.x + mz.y * hz.y;
       v[0][j] = hx; v[1][j] = hy; v[2][j] = hz;
     }
-    if (a.epart && valid) e = (double)(wkx * ef);
+    if (ENERGY && valid) e = (double)(wkx * ef);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       group_fft<M, R, true>(v[c], scr, t, tab);
@@ -321,12 +359,17 @@ k_mid(MidArgs a) {
       }
       __syncthreads();
     }
-    for (int q = tid; q < ny * KW; q += blockDim.x) {
-      const int y = q / KW, s = q - y * KW;
-      blk[(size_t)y * TILE + s] = stage[q];
+    {
+      constexpr int V = KW / 2;
+      const float4* st4 = reinterpret_cast<const float4*>(stage);
+      float4* b4 = reinterpret_cast<float4*>(blk);
+      for (int q = tid; q < ny * V; q += blockDim.x) {
+        const int y = q / V, s2 = q - y * V;
+        b4[(unsigned)y * (TILE / 2) + s2] = st4[q];
+      }
     }
   }
-  if (a.epart) {
+  if constexpr (ENERGY) {
     const double s = block_sum(e, red);
     if (tid == 0) a.epart[lg] = s;
   }
@@ -357,29 +400,30 @@ __global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_e
   // inverse z per (y, kx), keeping z < nz: the even kz residue, then the
   // odd one added through LDS (one residue live at a time)
   const int items = yg * Kx;
-  const size_t kzstride = (size_t)a.nTiles * ny * TILE;
+  const unsigned kzstride = (unsigned)a.nTiles * ny * TILE;
+  const float2* const Tc = a.T + (size_t)c * NZ * kzstride;
   for (int it = tid; it < items; it += INV_THREADS) {
     const int yl = it / Kx, kx = it - yl * Kx;
-    const int y = y0 + yl;
-    const float2* src = a.T + ((((size_t)c * NZ) * a.nTiles + kx / TILE) * ny + y) * TILE + (kx % TILE);
+    const unsigned o = ((unsigned)(kx / TILE) * ny + (y0 + yl)) * TILE + (kx % TILE);
+    float2* const d0 = &smem[(yl * nz) * PITCH + kx];
     if constexpr (NZ == 1) {
-      smem[(yl * nz) * PITCH + kx] = src[0];
+      d0[0] = Tc[o];
     } else {
       constexpr int Q = NZ / 2;
       float2 v[Q];
 #pragma unroll
-      for (int rz = 0; rz < 2; ++rz) {
+      for (int k = 0; k < Q; ++k) v[k] = Tc[o + (unsigned)(2 * k) * kzstride];
+      dft<Q, true>(v);
 #pragma unroll
-        for (int k = 0; k < Q; ++k) v[k] = src[(size_t)(2 * k + rz) * kzstride];
-        dft<Q, true>(v);
+      for (int z = 0; z < Q; ++z)
+        if (z < nz) d0[z * PITCH] = v[z];
 #pragma unroll
-        for (int z = 0; z < Q; ++z) {
-          if (z < nz) {
-            float2* d = &smem[(yl * nz + z) * PITCH + kx];
-            *d = rz ? cadd(*d, cmul(v[z], twiddle<true>(a.tw, z, LNZ))) : v[z];
-          }
-        }
-      }
+      for (int k = 0; k < Q; ++k) v[k] = Tc[o + (unsigned)(2 * k + 1) * kzstride];
+      dft<Q, true>(v);
+      zodd_twiddle<NZ, 0, true>(v);
+#pragma unroll
+      for (int z = 0; z < Q; ++z)
+        if (z < nz) d0[z * PITCH] = cadd(d0[z * PITCH], v[z]);
     }
   }
   __syncthreads();
@@ -568,14 +612,14 @@ hipError_t launch_fwd(const Geom& g, const FwdArgs& a, hipStream_t s) { DEMAG_X_
 hipError_t launch_inv(const Geom& g, const InvArgs& a, hipStream_t s) { DEMAG_X_SWITCH(inv_z, g, a, s) }
 
 int mid_kw(const Geom& g) {
-  if (g.mid_kw == 4 || g.mid_kw == 8) return g.mid_kw;
+  if (g.mid_kw == 2 || g.mid_kw == 4 || g.mid_kw == 8) return g.mid_kw;
   return 4;
 }
 
 int mid_blocks(const Geom& g) { return g.nTiles * (TILE / mid_kw(g)) * g.Nz; }
 
-template <int LNY, int KW>
-static hipError_t mid_one(const Geom& g, const MidArgs& a, hipStream_t s) {
+template <int LNY, int KW, bool ENERGY>
+static hipError_t mid_launch(const Geom& g, const MidArgs& a, hipStream_t s) {
   constexpr int NY = 1 << LNY;
   constexpr int M = NY > 1 ? NY / 2 : 1;
   constexpr int NRES = NY > 1 ? 2 : 1;
@@ -583,16 +627,24 @@ static hipError_t mid_one(const Geom& g, const MidArgs& a, hipStream_t s) {
   const size_t st = (size_t)g.ny * KW * sizeof(float2);
   if (st > lds) lds = st;
   lds += tab_points<M>() * sizeof(float2);
-  hipError_t e = prep_lds(k_mid<LNY, KW>, lds);
+  hipError_t e = prep_lds(k_mid<LNY, KW, ENERGY>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_mid<LNY, KW>), dim3(mid_blocks(g)), dim3(mid_threads(LNY, KW)), lds, s, a);
+  hipLaunchKernelGGL((k_mid<LNY, KW, ENERGY>), dim3(mid_blocks(g)), dim3(mid_threads(LNY, KW)), lds, s, a);
   return hipGetLastError();
+}
+
+template <int LNY, int KW>
+static hipError_t mid_one(const Geom& g, const MidArgs& a, hipStream_t s) {
+  return a.epart ? mid_launch<LNY, KW, true>(g, a, s) : mid_launch<LNY, KW, false>(g, a, s);
 }
 
 template <int LNY>
 static hipError_t mid_kw_switch(const Geom& g, const MidArgs& a, hipStream_t s) {
-  if (mid_kw(g) == 8) return mid_one<LNY, 8>(g, a, s);
-  return mid_one<LNY, 4>(g, a, s);
+  switch (mid_kw(g)) {
+    case 2: return mid_one<LNY, 2>(g, a, s);
+    case 8: return mid_one<LNY, 8>(g, a, s);
+    default: return mid_one<LNY, 4>(g, a, s);
+  }
 }
 
 hipError_t launch_mid(const Geom& g, const MidArgs& a, hipStream_t s) {
