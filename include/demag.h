@@ -18,8 +18,9 @@
  *  - Arguments and sizes are checked on the host before any HIP call.
  *  - Device pointers are allocated and owned by the caller; the library never
  *    frees them.  `stream` is a hipStream_t (NULL = the default stream).
- *  - demag_field, demag_energy and demag_backward only enqueue work on
- *    `stream`: they neither allocate nor synchronize.  Calls that share a
+ *  - demag_field(_batch), demag_energy and demag_backward(_batch) only
+ *    enqueue work on `stream`: they neither allocate nor synchronize, so a
+ *    caller may capture them in a HIP graph and replay it.  Calls that share a
  *    plan share its work buffer and must be ordered on one stream.
  *  - Arrays of vectors are SoA [3][nz][ny][nx], x fastest, FP32.  Lengths in
  *    metres, M and H in A/m, energies in joules (FP64).
@@ -100,6 +101,32 @@ int demag_energy(const demag_plan* plan, const float* d_m, const float* d_Ms, fl
  * d_G may alias neither d_H nor d_grad_m. */
 int demag_backward(const demag_plan* plan, const float* d_G, const float* d_Ms, float Ms, const float* d_H,
                    const double* d_gE, float* d_grad_m, unsigned flags, void* stream);
+
+/* Batches of independent meshes (Sec. 3: a collection of meshes V_k, each with
+ * its own discretization, evaluated together).  Mesh i has dims[3i..3i+2]
+ * cells of cells[3i..3i+2] metres; meshes of identical geometry share one
+ * kernel spectrum and are transformed by the same launches.  Vectors of all
+ * meshes are concatenated in mesh order, each mesh SoA [3][nz][ny][nx], at the
+ * float offsets given by demag_batch_layout.  Periodic flags return
+ * DEMAG_EUNSUPPORTED.  Host only, like demag_setup. */
+int demag_setup_batch(demag_plan** out, int nmesh, const int* dims, const double* cells, unsigned pbc_flags,
+                      int pbc_images);
+
+/* Number of meshes, float offset of each mesh's block (offsets may be NULL;
+ * otherwise room for nmesh entries) and total floats of one batch vector. */
+int demag_batch_layout(const demag_plan* plan, int* nmesh, long long* offsets, size_t* total_floats);
+
+/* H_d of every mesh of a batch plan in one launch sequence (one launch per
+ * pass and geometry).  d_Ms_mesh: device float[nmesh] saturation
+ * magnetizations, or NULL for the scalar Ms; d_energy: NULL or device
+ * double[nmesh].  Otherwise as demag_field. */
+int demag_field_batch(const demag_plan* plan, const float* d_m, const float* d_Ms_mesh, float Ms, float* d_H,
+                      unsigned flags, double* d_energy, void* stream);
+
+/* demag_backward for every mesh of a batch plan; d_gE: NULL or device
+ * double[nmesh]. */
+int demag_backward_batch(const demag_plan* plan, const float* d_G, const float* d_Ms_mesh, float Ms,
+                         const float* d_H, const double* d_gE, float* d_grad_m, unsigned flags, void* stream);
 
 /* Per-pass timing: `events` points to 4 hipEvent_t created by the caller; each
  * later demag_field / demag_backward call on this plan records them on its

@@ -1,5 +1,10 @@
 // C ABI of the demagnetizing-field library: argument checks, plan geometry,
 // kernel-spectrum set-up and the launch sequence of one field evaluation.
+//
+// A plan holds one or more sub-plans, each a group of meshes with identical
+// geometry that share one kernel spectrum and run through the same three
+// passes with a batch dimension.  A single-mesh plan is one sub-plan with one
+// member and no offset tables.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -17,16 +22,32 @@
 
 using namespace demag;
 
+namespace {
+
+struct Sub {
+  Geom g{};
+  std::vector<int> members;          // global mesh ids
+  size_t k_off = 0, tab_off = 0;     // offsets into the kernel buffer
+  size_t t_off = 0, e_off = 0;       // offsets into the work buffer
+  size_t parts = 0;                  // energy partials per member
+  float* K = nullptr;
+  long long* moff = nullptr;
+  int* gid = nullptr;
+  float2* T = nullptr;
+  double* epart = nullptr;
+};
+
+}  // namespace
+
 struct demag_plan {
-  Geom g;
+  std::vector<Sub> subs;
+  bool batch = false;
+  std::vector<long long> offsets;    // float offset of each mesh in concatenated buffers
+  size_t total_floats = 0;
   bool bound = false;
   int device = -1;
-  float2* tw = nullptr;    // twiddle table (start of the kernel buffer)
-  float* K = nullptr;      // kernel spectrum
-  float2* T = nullptr;     // spectrum work buffer
-  double* epart = nullptr; // energy partials
+  float2* tw = nullptr;
   size_t kernel_bytes = 0, work_bytes = 0;
-  size_t tw_bytes = 0, spec_bytes = 0, part_count = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool timing = false;
 };
@@ -94,25 +115,14 @@ void gauss_legendre(int n, double* x, double* w) {
 
 bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255) == 0; }
 
-}  // namespace
-
-extern "C" {
-
-const char* demag_last_error(void) { return g_err.c_str(); }
-
-int demag_setup(demag_plan** out, int nx, int ny, int nz, double dx, double dy, double dz, unsigned pbc_flags,
-                int pbc_images) {
-  (void)pbc_images;
-  if (!out) return fail(DEMAG_EINVAL, "demag_setup: out is NULL");
-  *out = nullptr;
-  if (nx < 1 || ny < 1 || nz < 1) return fail(DEMAG_EINVAL, "demag_setup: mesh dimensions must be >= 1");
+// Validate one mesh and derive its geometry (host only).
+int make_geom(int nx, int ny, int nz, double dx, double dy, double dz, Geom& g, const char* who) {
+  if (nx < 1 || ny < 1 || nz < 1) return fail(DEMAG_EINVAL, std::string(who) + ": mesh dimensions must be >= 1");
   if (!(std::isfinite(dx) && std::isfinite(dy) && std::isfinite(dz)) || dx <= 0 || dy <= 0 || dz <= 0)
-    return fail(DEMAG_EINVAL, "demag_setup: cell sizes must be finite and > 0");
-  if (pbc_flags & ~7u) return fail(DEMAG_EINVAL, "demag_setup: unknown boundary flags");
-  if (pbc_flags) return fail(DEMAG_EUNSUPPORTED, "demag_setup: periodic boundaries are not supported");
+    return fail(DEMAG_EINVAL, std::string(who) + ": cell sizes must be finite and > 0");
   if (nx > 2048 || ny > 1024 || nz > 16)
-    return fail(DEMAG_EUNSUPPORTED, "demag_setup: supported sizes are nx <= 2048, ny <= 1024, nz <= 16");
-  Geom g{};
+    return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": supported sizes are nx <= 2048, ny <= 1024, nz <= 16");
+  g = Geom{};
   g.nx = nx; g.ny = ny; g.nz = nz;
   g.Nx = padded(nx); g.Ny = padded(ny); g.Nz = padded(nz);
   g.lnx = ilog2i(g.Nx); g.lny = ilog2i(g.Ny); g.lnz = ilog2i(g.Nz);
@@ -124,7 +134,7 @@ int demag_setup(demag_plan** out, int nx, int ny, int nz, double dx, double dy, 
   const size_t pitch_bytes = (size_t)xrow_pitch_rt(g.lnx) * sizeof(float2);
   const size_t tab_bytes = 8192;   // stage twiddle table of the x passes (upper bound)
   if ((size_t)nz * pitch_bytes + tab_bytes > 160 * 1024)
-    return fail(DEMAG_EUNSUPPORTED, "demag_setup: the nz rows of one y line must fit in 160 KiB of LDS");
+    return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": the nz rows of one y line must fit in 160 KiB of LDS");
   // y rows per workgroup of the x passes: enough rows for one round of the
   // workgroup, within 64 KiB of LDS
   const int P = g.Nx >= 4 ? g.Nx / 4 : 1;
@@ -139,54 +149,34 @@ int demag_setup(demag_plan** out, int nx, int ny, int nz, double dx, double dy, 
     const int v = std::atoi(kw);
     g.mid_kw = (v == 2 || v == 8) ? v : 4;
   }
-
-  demag_plan* p = new (std::nothrow) demag_plan;
-  if (!p) return fail(DEMAG_ENOMEM, "demag_setup: out of host memory");
-  p->g = g;
-  p->tw_bytes = align256((size_t)TW_SIZE * sizeof(float2));
-  p->spec_bytes = align256((size_t)6 * g.Kzh * g.Kyh * g.Kx * sizeof(float));
-  p->kernel_bytes = p->tw_bytes + p->spec_bytes;
-  const size_t ncell = (size_t)nx * ny * nz;
-  p->part_count = (size_t)mid_blocks(g);
-  const size_t ecb = (size_t)energy_cell_blocks(ncell);
-  if (ecb > p->part_count) p->part_count = ecb;
-  p->work_bytes = align256(spectrum_elems(g) * sizeof(float2)) + align256(p->part_count * sizeof(double));
-  *out = p;
   return DEMAG_OK;
 }
 
-int demag_padded_dims(const demag_plan* p, int* Nx, int* Ny, int* Nz) {
-  if (!p || !Nx || !Ny || !Nz) return fail(DEMAG_EINVAL, "demag_padded_dims: NULL argument");
-  *Nx = p->g.Nx; *Ny = p->g.Ny; *Nz = p->g.Nz;
-  return DEMAG_OK;
-}
-
-int demag_buffer_bytes(const demag_plan* p, size_t* kernel_bytes, size_t* work_bytes) {
-  if (!p || !kernel_bytes || !work_bytes) return fail(DEMAG_EINVAL, "demag_buffer_bytes: NULL argument");
-  *kernel_bytes = p->kernel_bytes;
-  *work_bytes = p->work_bytes;
-  return DEMAG_OK;
-}
-
-int demag_bind(demag_plan* p, void* d_kernel, void* d_work, void* stream) {
-  if (!p) return fail(DEMAG_EINVAL, "demag_bind: plan is NULL");
-  if (p->bound) return fail(DEMAG_ESTATE, "demag_bind: plan is already bound");
-  if (!d_kernel || !d_work) return fail(DEMAG_EINVAL, "demag_bind: NULL buffer");
-  if (!aligned(d_kernel) || !aligned(d_work)) return fail(DEMAG_EINVAL, "demag_bind: buffers must be 256-byte aligned");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const Geom& g = p->g;
-  hipError_t e = hipGetDevice(&p->device);
-  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
-
-  // twiddles W_4096^k in FP64, rounded once to FP32
-  std::vector<float2> tw(TW_SIZE);
-  for (int k = 0; k < TW_SIZE; ++k) {
-    const double ang = -2.0 * M_PI * k / TW_SIZE;
-    tw[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+// Buffer layout of a plan (sizes only; pointers are attached at bind).
+void layout(demag_plan* p) {
+  size_t kb = align256((size_t)TW_SIZE * sizeof(float2));
+  size_t wb = 0;
+  for (Sub& s : p->subs) {
+    const Geom& g = s.g;
+    const size_t nb = s.members.size();
+    s.k_off = kb;
+    kb += align256((size_t)6 * g.Kzh * g.Kyh * g.Kx * sizeof(float));
+    s.tab_off = kb;
+    kb += align256(nb * sizeof(long long)) + align256(nb * sizeof(int));
+    s.t_off = wb;
+    wb += align256(nb * spectrum_elems(g) * sizeof(float2));
+    const size_t ncell = (size_t)g.nx * g.ny * g.nz;
+    s.parts = (size_t)mid_blocks(g);
+    const size_t ecb = (size_t)energy_cell_blocks(ncell);
+    if (ecb > s.parts) s.parts = ecb;
+    s.e_off = wb;
+    wb += align256(nb * s.parts * sizeof(double));
   }
-  float2* d_tw = static_cast<float2*>(d_kernel);
-  float* d_K = reinterpret_cast<float*>(static_cast<char*>(d_kernel) + p->tw_bytes);
+  p->kernel_bytes = kb;
+  p->work_bytes = wb;
+}
 
+int build_spectrum(const Geom& g, float* d_K, hipStream_t s) {
   // FP64 cos/sin tables per axis
   const int Ns[3] = {g.Nx, g.Ny, g.Nz};
   int Nmax = 1;
@@ -198,7 +188,6 @@ int demag_bind(demag_plan* p, void* d_kernel, void* d_work, void* stream) {
       trig[(size_t)(2 * a) * Nmax + m] = std::cos(ang);
       trig[(size_t)(2 * a + 1) * Nmax + m] = std::sin(ang);
     }
-
   GLTable gl{};
   const int orders[4] = {8, 6, 4, 3};
   for (int b = 0; b < 4; ++b) {
@@ -210,8 +199,6 @@ int demag_bind(demag_plan* p, void* d_kernel, void* d_work, void* stream) {
       gl.w[b][i] = 0.5 * w[i];
     }
   }
-
-  // FP64 temporaries (set-up only)
   const size_t s0 = (size_t)g.nz * g.ny * g.nx;
   const size_t s1 = (size_t)g.nz * g.ny * g.Kx;
   const size_t s2 = (size_t)g.nz * g.Kyh * g.Kx;
@@ -220,10 +207,8 @@ int demag_bind(demag_plan* p, void* d_kernel, void* d_work, void* stream) {
   for (size_t v : {s1, s2, s3}) smax = v > smax ? v : smax;
   double *bufA = nullptr, *bufB = nullptr, *d_trig = nullptr;
   int rc = DEMAG_OK;
+  hipError_t e;
   do {
-    if ((e = hipMemcpyAsync(d_tw, tw.data(), TW_SIZE * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess) {
-      rc = fail_hip(e, "twiddle upload"); break;
-    }
     if (hipMalloc(&bufA, 6 * smax * sizeof(double)) != hipSuccess ||
         hipMalloc(&bufB, 6 * smax * sizeof(double)) != hipSuccess ||
         hipMalloc(&d_trig, trig.size() * sizeof(double)) != hipSuccess) {
@@ -255,72 +240,246 @@ int demag_bind(demag_plan* p, void* d_kernel, void* d_work, void* stream) {
   if (bufA) (void)hipFree(bufA);
   if (bufB) (void)hipFree(bufB);
   if (d_trig) (void)hipFree(d_trig);
-  if (rc != DEMAG_OK) return rc;
-
-  p->tw = d_tw;
-  p->K = d_K;
-  p->T = static_cast<float2*>(d_work);
-  p->epart = reinterpret_cast<double*>(static_cast<char*>(d_work) + align256(spectrum_elems(g) * sizeof(float2)));
-  p->bound = true;
-  return DEMAG_OK;
+  return rc;
 }
 
-static int mark(const demag_plan* p, int i, hipStream_t s) {
+int mark(const demag_plan* p, int i, hipStream_t s) {
   if (!p->timing) return DEMAG_OK;
   hipError_t e = hipEventRecord(p->ev[i], s);
   return e == hipSuccess ? DEMAG_OK : fail_hip(e, "hipEventRecord");
 }
 
-static int run_conv(const demag_plan* p, const float* src, const float* Ms, float ms, double* epart, hipStream_t s) {
-  const Geom& g = p->g;
+// forward and middle passes of one sub-plan
+int run_conv(const demag_plan* p, const Sub& sb, const float* src, const float* Ms, float ms,
+             const float* ms_mesh, bool energy, hipStream_t s) {
+  const Geom& g = sb.g;
+  const int nb = (int)sb.members.size();
+  const long long* moff = p->batch ? sb.moff : nullptr;
+  const int* gid = p->batch ? sb.gid : nullptr;
+  const size_t Tb = spectrum_elems(g);
   int rc = mark(p, 0, s);
   if (rc != DEMAG_OK) return rc;
-  FwdArgs fa{src, Ms, ms, p->T, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg};
+  FwdArgs fa{src, Ms, ms, sb.T, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, nb, moff, ms_mesh, Tb, gid};
   hipError_t e = launch_fwd(g, fa, s);
   if (e != hipSuccess) return fail_hip(e, "forward pass");
   if ((rc = mark(p, 1, s)) != DEMAG_OK) return rc;
-  MidArgs ma{p->T, p->K, p->tw, epart, g.ny, g.Nz, g.Nx, g.nTiles, g.Kx, g.Kyh, g.Kzh, TILE / mid_kw(g)};
+  MidArgs ma{sb.T, sb.K, p->tw, energy ? sb.epart : nullptr, g.ny, g.Nz, g.Nx, g.nTiles, g.Kx, g.Kyh, g.Kzh,
+             TILE / mid_kw(g), nb, Tb, mid_blocks(g)};
   e = launch_mid(g, ma, s);
   if (e != hipSuccess) return fail_hip(e, "middle pass");
   return mark(p, 2, s);
 }
 
+int run_field(const demag_plan* p, const float* d_m, const float* d_Ms, float Ms, const float* ms_mesh, float* d_H,
+              unsigned flags, double* d_energy, hipStream_t s) {
+  for (const Sub& sb : p->subs) {
+    const Geom& g = sb.g;
+    const int nb = (int)sb.members.size();
+    int rc = run_conv(p, sb, d_m, d_Ms, Ms, ms_mesh, d_energy != nullptr, s);
+    if (rc != DEMAG_OK) return rc;
+    InvArgs ia{sb.T, d_H, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, (flags & DEMAG_ACCUMULATE) ? 1 : 0,
+               nullptr, nullptr, 0.0, nullptr, 0.f, 0,
+               nb, p->batch ? sb.moff : nullptr, ms_mesh, spectrum_elems(g), p->batch ? sb.gid : nullptr};
+    hipError_t e = launch_inv(g, ia, s);
+    if (e != hipSuccess) return fail_hip(e, "inverse pass");
+    if ((rc = mark(p, 3, s)) != DEMAG_OK) return rc;
+    if (d_energy) {
+      const double V = g.dx * g.dy * g.dz;
+      e = launch_energy_final(sb.epart, mid_blocks(g), -0.5 * MU0 * V, d_energy, s, nb, p->batch ? sb.gid : nullptr);
+      if (e != hipSuccess) return fail_hip(e, "energy reduction");
+    }
+  }
+  return DEMAG_OK;
+}
+
+int run_backward(const demag_plan* p, const float* d_G, const float* d_Ms, float Ms, const float* ms_mesh,
+                 const float* d_H, const double* d_gE, float* d_grad, unsigned flags, hipStream_t s) {
+  for (const Sub& sb : p->subs) {
+    const Geom& g = sb.g;
+    const int nb = (int)sb.members.size();
+    int rc = run_conv(p, sb, d_G, nullptr, 1.0f, nullptr, false, s);
+    if (rc != DEMAG_OK) return rc;
+    const double V = g.dx * g.dy * g.dz;
+    InvArgs ia{sb.T, d_grad, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, (flags & DEMAG_ACCUMULATE) ? 1 : 0,
+               d_H, d_gE, -MU0 * V, d_Ms, Ms, 1,
+               nb, p->batch ? sb.moff : nullptr, ms_mesh, spectrum_elems(g), p->batch ? sb.gid : nullptr};
+    hipError_t e = launch_inv(g, ia, s);
+    if (e != hipSuccess) return fail_hip(e, "inverse pass");
+    if ((rc = mark(p, 3, s)) != DEMAG_OK) return rc;
+  }
+  return DEMAG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* demag_last_error(void) { return g_err.c_str(); }
+
+int demag_setup(demag_plan** out, int nx, int ny, int nz, double dx, double dy, double dz, unsigned pbc_flags,
+                int pbc_images) {
+  (void)pbc_images;
+  if (!out) return fail(DEMAG_EINVAL, "demag_setup: out is NULL");
+  *out = nullptr;
+  Geom g;
+  int rc = make_geom(nx, ny, nz, dx, dy, dz, g, "demag_setup");
+  if (rc != DEMAG_OK) return rc;
+  if (pbc_flags & ~7u) return fail(DEMAG_EINVAL, "demag_setup: unknown boundary flags");
+  if (pbc_flags) return fail(DEMAG_EUNSUPPORTED, "demag_setup: periodic boundaries are not supported");
+  demag_plan* p = new (std::nothrow) demag_plan;
+  if (!p) return fail(DEMAG_ENOMEM, "demag_setup: out of host memory");
+  Sub sb;
+  sb.g = g;
+  sb.members = {0};
+  p->subs.push_back(sb);
+  p->offsets = {0};
+  p->total_floats = (size_t)3 * nx * ny * nz;
+  layout(p);
+  *out = p;
+  return DEMAG_OK;
+}
+
+int demag_setup_batch(demag_plan** out, int nmesh, const int* dims, const double* cells, unsigned pbc_flags,
+                      int pbc_images) {
+  (void)pbc_images;
+  if (!out) return fail(DEMAG_EINVAL, "demag_setup_batch: out is NULL");
+  *out = nullptr;
+  if (nmesh < 1 || !dims || !cells) return fail(DEMAG_EINVAL, "demag_setup_batch: need nmesh >= 1 and dims/cells");
+  if (pbc_flags & ~7u) return fail(DEMAG_EINVAL, "demag_setup_batch: unknown boundary flags");
+  if (pbc_flags) return fail(DEMAG_EUNSUPPORTED, "demag_setup_batch: periodic boundaries are not supported");
+  demag_plan* p = new (std::nothrow) demag_plan;
+  if (!p) return fail(DEMAG_ENOMEM, "demag_setup_batch: out of host memory");
+  p->batch = true;
+  size_t off = 0;
+  for (int i = 0; i < nmesh; ++i) {
+    Geom g;
+    const int rc = make_geom(dims[3 * i], dims[3 * i + 1], dims[3 * i + 2], cells[3 * i], cells[3 * i + 1],
+                             cells[3 * i + 2], g, "demag_setup_batch");
+    if (rc != DEMAG_OK) {
+      delete p;
+      return rc;
+    }
+    p->offsets.push_back((long long)off);
+    off += (size_t)3 * g.nx * g.ny * g.nz;
+    bool placed = false;
+    for (Sub& sb : p->subs) {
+      const Geom& h = sb.g;
+      if (h.nx == g.nx && h.ny == g.ny && h.nz == g.nz && h.dx == g.dx && h.dy == g.dy && h.dz == g.dz) {
+        sb.members.push_back(i);
+        placed = true;
+        break;
+      }
+    }
+    if (!placed) {
+      Sub sb;
+      sb.g = g;
+      sb.members = {i};
+      p->subs.push_back(sb);
+    }
+  }
+  p->total_floats = off;
+  layout(p);
+  *out = p;
+  return DEMAG_OK;
+}
+
+int demag_batch_layout(const demag_plan* p, int* nmesh, long long* offsets, size_t* total_floats) {
+  if (!p || !nmesh || !total_floats) return fail(DEMAG_EINVAL, "demag_batch_layout: NULL argument");
+  *nmesh = (int)p->offsets.size();
+  *total_floats = p->total_floats;
+  if (offsets)
+    for (size_t i = 0; i < p->offsets.size(); ++i) offsets[i] = p->offsets[i];
+  return DEMAG_OK;
+}
+
+int demag_padded_dims(const demag_plan* p, int* Nx, int* Ny, int* Nz) {
+  if (!p || !Nx || !Ny || !Nz) return fail(DEMAG_EINVAL, "demag_padded_dims: NULL argument");
+  *Nx = p->subs[0].g.Nx; *Ny = p->subs[0].g.Ny; *Nz = p->subs[0].g.Nz;
+  return DEMAG_OK;
+}
+
+int demag_buffer_bytes(const demag_plan* p, size_t* kernel_bytes, size_t* work_bytes) {
+  if (!p || !kernel_bytes || !work_bytes) return fail(DEMAG_EINVAL, "demag_buffer_bytes: NULL argument");
+  *kernel_bytes = p->kernel_bytes;
+  *work_bytes = p->work_bytes;
+  return DEMAG_OK;
+}
+
+int demag_bind(demag_plan* p, void* d_kernel, void* d_work, void* stream) {
+  if (!p) return fail(DEMAG_EINVAL, "demag_bind: plan is NULL");
+  if (p->bound) return fail(DEMAG_ESTATE, "demag_bind: plan is already bound");
+  if (!d_kernel || !d_work) return fail(DEMAG_EINVAL, "demag_bind: NULL buffer");
+  if (!aligned(d_kernel) || !aligned(d_work)) return fail(DEMAG_EINVAL, "demag_bind: buffers must be 256-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  char* kb = static_cast<char*>(d_kernel);
+  char* wb = static_cast<char*>(d_work);
+
+  // twiddles W_4096^k in FP64, rounded once to FP32
+  std::vector<float2> tw(TW_SIZE);
+  for (int k = 0; k < TW_SIZE; ++k) {
+    const double ang = -2.0 * M_PI * k / TW_SIZE;
+    tw[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+  if ((e = hipMemcpyAsync(kb, tw.data(), TW_SIZE * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess)
+    return fail_hip(e, "twiddle upload");
+  for (Sub& sb : p->subs) {
+    sb.K = reinterpret_cast<float*>(kb + sb.k_off);
+    sb.moff = reinterpret_cast<long long*>(kb + sb.tab_off);
+    sb.gid = reinterpret_cast<int*>(kb + sb.tab_off + align256(sb.members.size() * sizeof(long long)));
+    sb.T = reinterpret_cast<float2*>(wb + sb.t_off);
+    sb.epart = reinterpret_cast<double*>(wb + sb.e_off);
+    std::vector<long long> mo;
+    for (int m : sb.members) mo.push_back(p->offsets[m]);
+    if ((e = hipMemcpyAsync(sb.moff, mo.data(), mo.size() * sizeof(long long), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(sb.gid, sb.members.data(), sb.members.size() * sizeof(int), hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+      return fail_hip(e, "batch table upload");
+    const int rc = build_spectrum(sb.g, sb.K, s);
+    if (rc != DEMAG_OK) return rc;
+  }
+  p->tw = reinterpret_cast<float2*>(kb);
+  p->bound = true;
+  return DEMAG_OK;
+}
+
 int demag_field(const demag_plan* p, const float* d_m, const float* d_Ms, float Ms, float* d_H, unsigned flags,
                 double* d_energy, void* stream) {
   if (!p) return fail(DEMAG_EINVAL, "demag_field: plan is NULL");
+  if (p->batch) return fail(DEMAG_EINVAL, "demag_field: batch plans use demag_field_batch");
   if (!p->bound) return fail(DEMAG_ESTATE, "demag_field: plan is not bound");
   if (!d_m || !d_H) return fail(DEMAG_EINVAL, "demag_field: NULL m or H");
   if (flags & ~(unsigned)DEMAG_ACCUMULATE) return fail(DEMAG_EINVAL, "demag_field: unknown flags");
   if (!d_Ms && !std::isfinite(Ms)) return fail(DEMAG_EINVAL, "demag_field: Ms is not finite");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const Geom& g = p->g;
-  int rc = run_conv(p, d_m, d_Ms, Ms, d_energy ? p->epart : nullptr, s);
-  if (rc != DEMAG_OK) return rc;
-  InvArgs ia{p->T, d_H, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, (flags & DEMAG_ACCUMULATE) ? 1 : 0,
-             nullptr, nullptr, 0.0, nullptr, 0.f, 0};
-  hipError_t e = launch_inv(g, ia, s);
-  if (e != hipSuccess) return fail_hip(e, "inverse pass");
-  if ((rc = mark(p, 3, s)) != DEMAG_OK) return rc;
-  if (d_energy) {
-    const double V = g.dx * g.dy * g.dz;
-    e = launch_energy_final(p->epart, mid_blocks(g), -0.5 * MU0 * V, d_energy, s);
-    if (e != hipSuccess) return fail_hip(e, "energy reduction");
-  }
-  return DEMAG_OK;
+  return run_field(p, d_m, d_Ms, Ms, nullptr, d_H, flags, d_energy, static_cast<hipStream_t>(stream));
+}
+
+int demag_field_batch(const demag_plan* p, const float* d_m, const float* d_Ms_mesh, float Ms, float* d_H,
+                      unsigned flags, double* d_energy, void* stream) {
+  if (!p) return fail(DEMAG_EINVAL, "demag_field_batch: plan is NULL");
+  if (!p->batch) return fail(DEMAG_EINVAL, "demag_field_batch: not a batch plan");
+  if (!p->bound) return fail(DEMAG_ESTATE, "demag_field_batch: plan is not bound");
+  if (!d_m || !d_H) return fail(DEMAG_EINVAL, "demag_field_batch: NULL m or H");
+  if (flags & ~(unsigned)DEMAG_ACCUMULATE) return fail(DEMAG_EINVAL, "demag_field_batch: unknown flags");
+  if (!d_Ms_mesh && !std::isfinite(Ms)) return fail(DEMAG_EINVAL, "demag_field_batch: Ms is not finite");
+  return run_field(p, d_m, nullptr, Ms, d_Ms_mesh, d_H, flags, d_energy, static_cast<hipStream_t>(stream));
 }
 
 int demag_energy(const demag_plan* p, const float* d_m, const float* d_Ms, float Ms, const float* d_H,
                  double* d_energy, void* stream) {
   if (!p) return fail(DEMAG_EINVAL, "demag_energy: plan is NULL");
+  if (p->batch) return fail(DEMAG_EINVAL, "demag_energy: single-mesh plans only");
   if (!p->bound) return fail(DEMAG_ESTATE, "demag_energy: plan is not bound");
   if (!d_m || !d_H || !d_energy) return fail(DEMAG_EINVAL, "demag_energy: NULL argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const Geom& g = p->g;
+  const Sub& sb = p->subs[0];
+  const Geom& g = sb.g;
   const size_t ncell = (size_t)g.nx * g.ny * g.nz;
-  hipError_t e = launch_energy_cells(d_m, d_Ms, Ms, d_H, ncell, p->epart, s);
+  hipError_t e = launch_energy_cells(d_m, d_Ms, Ms, d_H, ncell, sb.epart, s);
   if (e != hipSuccess) return fail_hip(e, "energy partials");
   const double V = g.dx * g.dy * g.dz;
-  e = launch_energy_final(p->epart, energy_cell_blocks(ncell), -0.5 * MU0 * V, d_energy, s);
+  e = launch_energy_final(sb.epart, energy_cell_blocks(ncell), -0.5 * MU0 * V, d_energy, s);
   if (e != hipSuccess) return fail_hip(e, "energy reduction");
   return DEMAG_OK;
 }
@@ -328,20 +487,23 @@ int demag_energy(const demag_plan* p, const float* d_m, const float* d_Ms, float
 int demag_backward(const demag_plan* p, const float* d_G, const float* d_Ms, float Ms, const float* d_H,
                    const double* d_gE, float* d_grad_m, unsigned flags, void* stream) {
   if (!p) return fail(DEMAG_EINVAL, "demag_backward: plan is NULL");
+  if (p->batch) return fail(DEMAG_EINVAL, "demag_backward: batch plans use demag_backward_batch");
   if (!p->bound) return fail(DEMAG_ESTATE, "demag_backward: plan is not bound");
   if (!d_G || !d_grad_m) return fail(DEMAG_EINVAL, "demag_backward: NULL G or grad_m");
   if (d_gE && !d_H) return fail(DEMAG_EINVAL, "demag_backward: the energy term needs the forward field H");
   if (flags & ~(unsigned)DEMAG_ACCUMULATE) return fail(DEMAG_EINVAL, "demag_backward: unknown flags");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const Geom& g = p->g;
-  int rc = run_conv(p, d_G, nullptr, 1.0f, nullptr, s);
-  if (rc != DEMAG_OK) return rc;
-  const double V = g.dx * g.dy * g.dz;
-  InvArgs ia{p->T, d_grad_m, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, (flags & DEMAG_ACCUMULATE) ? 1 : 0,
-             d_H, d_gE, -MU0 * V, d_Ms, Ms, 1};
-  hipError_t e = launch_inv(g, ia, s);
-  if (e != hipSuccess) return fail_hip(e, "inverse pass");
-  return mark(p, 3, s);
+  return run_backward(p, d_G, d_Ms, Ms, nullptr, d_H, d_gE, d_grad_m, flags, static_cast<hipStream_t>(stream));
+}
+
+int demag_backward_batch(const demag_plan* p, const float* d_G, const float* d_Ms_mesh, float Ms, const float* d_H,
+                         const double* d_gE, float* d_grad_m, unsigned flags, void* stream) {
+  if (!p) return fail(DEMAG_EINVAL, "demag_backward_batch: plan is NULL");
+  if (!p->batch) return fail(DEMAG_EINVAL, "demag_backward_batch: not a batch plan");
+  if (!p->bound) return fail(DEMAG_ESTATE, "demag_backward_batch: plan is not bound");
+  if (!d_G || !d_grad_m) return fail(DEMAG_EINVAL, "demag_backward_batch: NULL G or grad_m");
+  if (d_gE && !d_H) return fail(DEMAG_EINVAL, "demag_backward_batch: the energy term needs the forward field H");
+  if (flags & ~(unsigned)DEMAG_ACCUMULATE) return fail(DEMAG_EINVAL, "demag_backward_batch: unknown flags");
+  return run_backward(p, d_G, nullptr, Ms, d_Ms_mesh, d_H, d_gE, d_grad_m, flags, static_cast<hipStream_t>(stream));
 }
 
 int demag_set_timing_events(demag_plan* p, void* const* events, int count) {

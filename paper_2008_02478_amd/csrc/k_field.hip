@@ -60,7 +60,12 @@ __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_e
   constexpr int NZ = 1 << LNZ;
   extern __shared__ float2 smem_base[];
   const int nyb = (a.ny + a.yg - 1) / a.yg;
-  const int lg = xcd_logical(blockIdx.x, gridDim.x);
+  const int lg0 = xcd_logical(blockIdx.x, gridDim.x);
+  const int b = lg0 / (3 * nyb);            // batch member
+  const int lg = lg0 - b * 3 * nyb;
+  if (a.moff) a.m += a.moff[b];
+  if (a.ms_mesh) a.ms = a.ms_mesh[a.gid ? a.gid[b] : b];
+  a.T += (size_t)b * a.Tb;
   const int c = lg / nyb;
   const int y0 = (lg - c * nyb) * a.yg;
   const int yg = min(a.yg, a.ny - y0);
@@ -243,8 +248,11 @@ k_mid(MidArgs a) {
   float2* const tab = smem_base;
   float2* const smem = smem_base + tab_points<M>();
 
-  const int nblk = gridDim.x;
-  const int lg = xcd_logical(blockIdx.x, nblk);
+  const int lg0 = xcd_logical(blockIdx.x, gridDim.x);
+  const int bm = lg0 / a.nblk1;             // batch member
+  const int lg = lg0 - bm * a.nblk1;
+  a.T += (size_t)bm * a.Tb;
+  if (ENERGY) a.epart += (size_t)bm * a.nblk1;
   const int halves = a.kw_halves;
   const int half = lg % halves;
   const int kzi = (lg / halves) % a.Nz;
@@ -384,7 +392,16 @@ __global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_e
   constexpr int NZ = 1 << LNZ;
   extern __shared__ float2 smem_base[];
   const int nyb = (a.ny + a.yg - 1) / a.yg;
-  const int lg = xcd_logical(blockIdx.x, gridDim.x);
+  const int lg0 = xcd_logical(blockIdx.x, gridDim.x);
+  const int b = lg0 / (3 * nyb);            // batch member
+  const int lg = lg0 - b * 3 * nyb;
+  if (a.moff) {
+    a.H += a.moff[b];
+    if (a.aux) a.aux += a.moff[b];
+  }
+  if (a.ms_mesh) a.ms = a.ms_mesh[a.gid ? a.gid[b] : b];
+  if (a.beta_ptr && a.gid) a.beta_ptr += a.gid[b];
+  a.T += (size_t)b * a.Tb;
   const int c = lg / nyb;
   const int y0 = (lg - c * nyb) * a.yg;
   const int yg = min(a.yg, a.ny - y0);
@@ -513,13 +530,16 @@ __global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_e
 // ---------------------------------------------------------------------------
 // Sum of the middle pass' Parseval partials in a fixed order:
 // E = scale * sum(partials), scale = -(mu0/2) V.
+// One workgroup per batch member; out index gid[member] (or the member).
 __global__ void __launch_bounds__(RED_THREADS) k_energy_final(const double* part, int n, double scale,
-                                                              double* out) {
+                                                              double* out, const int* gid) {
   __shared__ double red[RED_THREADS / 64];
+  const int b = blockIdx.x;
+  part += (size_t)b * n;
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += RED_THREADS) s += part[i];
   s = block_sum(s, red);
-  if (threadIdx.x == 0) *out = scale * s;
+  if (threadIdx.x == 0) out[gid ? gid[b] : b] = scale * s;
 }
 
 // Per-workgroup partials of sum_c Ms m_c H_c over the cells.
@@ -561,7 +581,7 @@ static hipError_t fwd_one(const Geom& g, const FwdArgs& a, hipStream_t s) {
   const size_t lds = xpass_lds(g) + xtab_points<LNX>() * sizeof(float2);
   hipError_t e = prep_lds(k_fwd_xz<LNX, LNZ>, lds);
   if (e != hipSuccess) return e;
-  dim3 grid(((g.ny + g.yg - 1) / g.yg) * 3);
+  dim3 grid(((g.ny + g.yg - 1) / g.yg) * 3 * a.nb);
   hipLaunchKernelGGL((k_fwd_xz<LNX, LNZ>), grid, dim3(FWD_THREADS), lds, s, a);
   return hipGetLastError();
 }
@@ -571,7 +591,7 @@ static hipError_t inv_one(const Geom& g, const InvArgs& a, hipStream_t s) {
   const size_t lds = xpass_lds(g) + xtab_points<LNX>() * sizeof(float2);
   hipError_t e = prep_lds(k_inv_zx<LNX, LNZ>, lds);
   if (e != hipSuccess) return e;
-  dim3 grid(((g.ny + g.yg - 1) / g.yg) * 3);
+  dim3 grid(((g.ny + g.yg - 1) / g.yg) * 3 * a.nb);
   hipLaunchKernelGGL((k_inv_zx<LNX, LNZ>), grid, dim3(INV_THREADS), lds, s, a);
   return hipGetLastError();
 }
@@ -629,7 +649,7 @@ static hipError_t mid_launch(const Geom& g, const MidArgs& a, hipStream_t s) {
   lds += tab_points<M>() * sizeof(float2);
   hipError_t e = prep_lds(k_mid<LNY, KW, ENERGY>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_mid<LNY, KW, ENERGY>), dim3(mid_blocks(g)), dim3(mid_threads(LNY, KW)), lds, s, a);
+  hipLaunchKernelGGL((k_mid<LNY, KW, ENERGY>), dim3(mid_blocks(g) * a.nb), dim3(mid_threads(LNY, KW)), lds, s, a);
   return hipGetLastError();
 }
 
@@ -664,8 +684,9 @@ hipError_t launch_mid(const Geom& g, const MidArgs& a, hipStream_t s) {
   }
 }
 
-hipError_t launch_energy_final(const double* part, int n, double scale, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(RED_THREADS), 0, s, part, n, scale, out);
+hipError_t launch_energy_final(const double* part, int n, double scale, double* out, hipStream_t s, int nb,
+                               const int* gid) {
+  hipLaunchKernelGGL(k_energy_final, dim3(nb), dim3(RED_THREADS), 0, s, part, n, scale, out, gid);
   return hipGetLastError();
 }
 

@@ -54,16 +54,24 @@ struct GLTable {
   int n[4];
 };
 
+// Batches: nb meshes of one geometry share the kernel spectrum.  Member b
+// reads and writes its vectors at moff[b] floats into the caller's
+// concatenated buffers (moff == nullptr: offset 0), uses Ms = ms_mesh[b]
+// (ms_mesh == nullptr: the scalar ms), its spectrum slab at b * Tb points and
+// its energy partials at b * (partials per member).
+
 struct FwdArgs {
   const float* m; const float* Ms; float ms;
   float2* T; const float2* tw;
   int nx, ny, nz, nTiles, Kx, yg;
+  int nb; const long long* moff; const float* ms_mesh; size_t Tb; const int* gid;
 };
 
 struct MidArgs {
   float2* T; const float* K; const float2* tw;
   double* epart;               // one partial per workgroup, or nullptr
   int ny, Nz, Nx, nTiles, Kx, Kyh, Kzh, kw_halves;
+  int nb; size_t Tb; int nblk1; // workgroups per member
 };
 
 struct InvArgs {
@@ -71,8 +79,9 @@ struct InvArgs {
   int nx, ny, nz, nTiles, Kx, yg;
   int accumulate;
   // optional epilogue for the backward: out = s * (conv + beta * aux), with
-  // s = per-cell Ms (or the scalar) and beta = *beta_ptr (device scalar)
+  // s = per-cell Ms (or the scalar) and beta = beta_scale * beta_ptr[member]
   const float* aux; const double* beta_ptr; double beta_scale; const float* Ms; float ms; int scale_out;
+  int nb; const long long* moff; const float* ms_mesh; size_t Tb; const int* gid;
 };
 
 }  // namespace demag

@@ -115,6 +115,70 @@ class DemagPlan:
             self._p = None
 
 
+class DemagBatch:
+    """Batch of independent meshes: meshes = [((nx, ny, nz), (dx, dy, dz)), ...].
+    Vectors of all meshes are concatenated (mesh order, each SoA
+    [3][nz][ny][nx]) into one flat float32 tensor of `total` elements;
+    `view(x, i)` returns mesh i's block.  Meshes of equal geometry share one
+    kernel spectrum and run through the same launches."""
+
+    def __init__(self, meshes, device=None):
+        self._lib = _l.load()
+        self.meshes = [(tuple(int(v) for v in n), tuple(float(v) for v in h)) for n, h in meshes]
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        k = len(self.meshes)
+        dims = (ctypes.c_int * (3 * k))(*[v for n, _ in self.meshes for v in n])
+        cells = (ctypes.c_double * (3 * k))(*[v for _, h in self.meshes for v in h])
+        self._p = ctypes.c_void_p()
+        _l.check(self._lib.demag_setup_batch(ctypes.byref(self._p), k, dims, cells, 0, 0))
+        nm, tot = ctypes.c_int(), ctypes.c_size_t()
+        offs = (ctypes.c_longlong * k)()
+        _l.check(self._lib.demag_batch_layout(self._p, ctypes.byref(nm), offs, ctypes.byref(tot)))
+        self.offsets = [int(o) for o in offs]
+        self.total = tot.value
+        kb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        _l.check(self._lib.demag_buffer_bytes(self._p, ctypes.byref(kb), ctypes.byref(wb)))
+        with torch.cuda.device(self.device):
+            self._kbuf = torch.empty(kb.value + 256, dtype=torch.uint8, device=self.device)
+            self._wbuf = torch.empty(wb.value + 256, dtype=torch.uint8, device=self.device)
+            _l.check(self._lib.demag_bind(self._p, DemagPlan._aligned(self._kbuf), DemagPlan._aligned(self._wbuf),
+                                          _stream()))
+
+    def view(self, x, i):
+        (nx, ny, nz), _ = self.meshes[i]
+        o = self.offsets[i]
+        return x[o:o + 3 * nx * ny * nz].view(3, nz, ny, nx)
+
+    def _check(self, t, name):
+        if t.shape != (self.total,) or t.dtype != torch.float32 or not t.is_contiguous() or t.device != self.device:
+            raise ValueError(f"{name}: expected a contiguous float32 ({self.total},) tensor on {self.device}")
+
+    def field(self, m, Ms, out=None, accumulate=False, energy=False):
+        """Fields of all meshes; Ms is a float or a float32 tensor of one value per mesh."""
+        self._check(m, "m")
+        out = torch.empty_like(m) if out is None else out
+        self._check(out, "out")
+        msa, mss = (Ms, 0.0) if isinstance(Ms, torch.Tensor) else (None, float(Ms))
+        e = torch.empty(len(self.meshes), dtype=torch.float64, device=self.device) if energy else None
+        _l.check(self._lib.demag_field_batch(self._p, _ptr(m), _ptr(msa), mss, _ptr(out),
+                                             _l.ACCUMULATE if accumulate else 0, _ptr(e), _stream()))
+        return (out, e) if energy else out
+
+    def backward(self, G, Ms, H=None, gE=None, out=None):
+        self._check(G, "G")
+        out = torch.empty_like(G) if out is None else out
+        msa, mss = (Ms, 0.0) if isinstance(Ms, torch.Tensor) else (None, float(Ms))
+        _l.check(self._lib.demag_backward_batch(self._p, _ptr(G), _ptr(msa), mss, _ptr(H) if gE is not None else None,
+                                                _ptr(gE), _ptr(out), 0, _stream()))
+        return out
+
+    def __del__(self):
+        p = getattr(self, "_p", None)
+        if p is not None and p.value:
+            self._lib.demag_destroy(p)
+            self._p = None
+
+
 class DemagFunction(torch.autograd.Function):
     """(H_d, E) = demag(m) for M = Ms m with a hand-written backward: the
     operator is self-adjoint, so the gradient of <G, H_d> is the same

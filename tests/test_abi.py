@@ -118,3 +118,44 @@ def test_timing_event_validation(lib):
         assert lib.demag_set_timing_events(p, None, 0) == L.OK
     finally:
         lib.demag_destroy(p)
+
+
+def test_batch_setup_and_layout(lib):
+    import numpy as np
+    dims = (ctypes.c_int * 9)(4, 3, 2, 8, 8, 1, 4, 3, 2)
+    cells = (ctypes.c_double * 9)(1e-9, 1e-9, 1e-9, 5e-9, 5e-9, 3e-9, 1e-9, 1e-9, 1e-9)
+    p = ctypes.c_void_p()
+    assert lib.demag_setup_batch(ctypes.byref(p), 3, dims, cells, 0, 0) == L.OK
+    try:
+        nm, tot = ctypes.c_int(), ctypes.c_size_t()
+        offs = (ctypes.c_longlong * 3)()
+        assert lib.demag_batch_layout(p, ctypes.byref(nm), offs, ctypes.byref(tot)) == L.OK
+        assert nm.value == 3
+        assert list(offs) == [0, 3 * 24, 3 * 24 + 3 * 64]
+        assert tot.value == 3 * (24 + 64 + 24)
+        dummy = ctypes.c_void_p(256)
+        # single-mesh entry points refuse batch plans, batch calls need a bind first
+        assert lib.demag_field(p, dummy, None, 1.0, dummy, 0, None, None) == L.EINVAL
+        assert lib.demag_field_batch(p, dummy, None, 1.0, dummy, 0, None, None) == L.ESTATE
+    finally:
+        lib.demag_destroy(p)
+
+
+@pytest.mark.parametrize("n,code", [(0, L.EINVAL), (2, L.EUNSUPPORTED)])
+def test_batch_setup_rejects(lib, n, code):
+    dims = (ctypes.c_int * 6)(4, 3, 2, 4, 3, 17)
+    cells = (ctypes.c_double * 6)(1e-9, 1e-9, 1e-9, 1e-9, 1e-9, 1e-9)
+    p = ctypes.c_void_p()
+    assert lib.demag_setup_batch(ctypes.byref(p), n, dims, cells, 0, 0) == code
+    assert not p.value
+
+
+def test_single_plan_refuses_batch_calls(lib):
+    p = ctypes.c_void_p()
+    assert lib.demag_setup(ctypes.byref(p), 8, 8, 2, 1e-9, 1e-9, 1e-9, 0, 0) == L.OK
+    try:
+        dummy = ctypes.c_void_p(256)
+        assert lib.demag_field_batch(p, dummy, None, 1.0, dummy, 0, None, None) == L.EINVAL
+        assert lib.demag_backward_batch(p, dummy, None, 1.0, None, None, dummy, 0, None) == L.EINVAL
+    finally:
+        lib.demag_destroy(p)
