@@ -102,15 +102,22 @@ int demag_energy(const demag_plan* plan, const float* d_m, const float* d_Ms, fl
 int demag_backward(const demag_plan* plan, const float* d_G, const float* d_Ms, float Ms, const float* d_H,
                    const double* d_gE, float* d_grad_m, unsigned flags, void* stream);
 
-/* Batches of independent meshes (Sec. 3: a collection of meshes V_k, each with
- * its own discretization, evaluated together).  Mesh i has dims[3i..3i+2]
- * cells of cells[3i..3i+2] metres; meshes of identical geometry share one
- * kernel spectrum and are transformed by the same launches.  Vectors of all
- * meshes are concatenated in mesh order, each mesh SoA [3][nz][ny][nx], at the
- * float offsets given by demag_batch_layout.  Periodic flags return
- * DEMAG_EUNSUPPORTED.  Host only, like demag_setup. */
-int demag_setup_batch(demag_plan** out, int nmesh, const int* dims, const double* cells, unsigned pbc_flags,
-                      int pbc_images);
+/* A collection of meshes with independent discretizations (Sec. 3, Eq. 4).
+ * Mesh i has dims[3i..3i+2] cells of cells[3i..3i+2] metres, its lower corner
+ * at origins[3i..3i+2] (metres; NULL: all at the origin, only allowed without
+ * groups).  groups: NULL, or one id per mesh; meshes sharing an id >= 0 are
+ * coupled: each one's field includes the fields of the others through the
+ * inter-mesh tensors N(r, h_k, h_i), summed in the transform space.  A
+ * coupled group needs in-plane cell sizes that are power-of-two multiples of
+ * the finest one, origins on the finest in-plane lattice, at most 8 z planes
+ * in all and a fine lattice of at most 2048 x 1024 cells (else
+ * DEMAG_EUNSUPPORTED).  Other meshes (id < 0) are independent; those of
+ * identical geometry share one kernel spectrum and one launch per pass.
+ * Vectors of all meshes are concatenated in mesh order, each mesh SoA
+ * [3][nz][ny][nx], at the float offsets given by demag_batch_layout.
+ * Periodic flags return DEMAG_EUNSUPPORTED.  Host only, like demag_setup. */
+int demag_setup_batch(demag_plan** out, int nmesh, const int* dims, const double* cells, const double* origins,
+                      const int* groups, unsigned pbc_flags, int pbc_images);
 
 /* Number of meshes, float offset of each mesh's block (offsets may be NULL;
  * otherwise room for nmesh entries) and total floats of one batch vector. */
@@ -124,7 +131,8 @@ int demag_field_batch(const demag_plan* plan, const float* d_m, const float* d_M
                       unsigned flags, double* d_energy, void* stream);
 
 /* demag_backward for every mesh of a batch plan; d_gE: NULL or device
- * double[nmesh]. */
+ * double[nmesh].  For coupled meshes the adjoint follows from reciprocity,
+ * V_k N_ki(r) = V_i N_ik(-r): d<G,H>/dM_i = V_i H_i[G_k / V_k]. */
 int demag_backward_batch(const demag_plan* plan, const float* d_G, const float* d_Ms_mesh, float Ms,
                          const float* d_H, const double* d_gE, float* d_grad_m, unsigned flags, void* stream);
 

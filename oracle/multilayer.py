@@ -151,12 +151,22 @@ def field_at(meshes, Ms, targets):
 
 
 def field(meshes, Ms):
-    """H of every cell of every mesh by the direct sum (tiny meshes only).
+    """H of every cell of every mesh by the direct sum (small meshes only):
+    all target cells of mesh p against all source cells of mesh q at once.
     Returns a list of arrays (3, nz, ny, nx)."""
     res = []
-    for p, (n, h, o) in enumerate(meshes):
-        nx, ny, nz = n
-        tg = [(p, (k, j, i)) for k in range(nz) for j in range(ny) for i in range(nx)]
-        H = field_at(meshes, Ms, tg)
-        res.append(H.T.reshape(3, nz, ny, nx))
+    for p, (n_p, h_p, o_p) in enumerate(meshes):
+        Zt, Yt, Xt = (a.ravel() for a in centres(n_p, h_p, o_p))
+        H = np.zeros((3, Xt.size))
+        for (n_q, h_q, o_q), M in zip(meshes, Ms):
+            Zs, Ys, Xs = (a.ravel() for a in centres(n_q, h_q, o_q))
+            M = np.asarray(M, np.float64).reshape(3, -1)
+            N = tensor_unequal(Xt[:, None] - Xs[None, :], Yt[:, None] - Ys[None, :], Zt[:, None] - Zs[None, :],
+                               h_p, h_q)
+            xx, yy, zz, xy, xz, yz = N
+            H[0] -= xx @ M[0] + xy @ M[1] + xz @ M[2]
+            H[1] -= xy @ M[0] + yy @ M[1] + yz @ M[2]
+            H[2] -= xz @ M[0] + yz @ M[1] + zz @ M[2]
+        nx, ny, nz = n_p
+        res.append(H.reshape(3, nz, ny, nx))
     return res

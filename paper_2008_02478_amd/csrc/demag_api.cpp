@@ -7,6 +7,7 @@
 // member and no offset tables.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -37,10 +38,28 @@ struct Sub {
   double* epart = nullptr;
 };
 
+// A coupled group: planes of several meshes on one fine in-plane lattice.
+struct Group {
+  std::vector<int> members;
+  std::vector<PlaneInfo> planes;
+  std::vector<double> ph;          // 3 cell sizes per plane
+  std::vector<double> pdx, pdy, pz;
+  Geom g{};                        // fine lattice: nx = Lx, ny = Ly, nz = Nz = P
+  double fx = 0, fy = 0;
+  size_t k_off = 0, pl_off = 0, t_off = 0, s_off = 0, e_off = 0;
+  float2* K = nullptr;
+  PlaneInfo* pl = nullptr;
+  float2* T = nullptr;
+  float2* S = nullptr;
+  double* epart = nullptr;
+  int npairs() const { const int P = (int)planes.size(); return P * (P + 1) / 2; }
+};
+
 }  // namespace
 
 struct demag_plan {
   std::vector<Sub> subs;
+  std::vector<Group> groups;
   bool batch = false;
   std::vector<long long> offsets;    // float offset of each mesh in concatenated buffers
   size_t total_floats = 0;
@@ -172,8 +191,185 @@ void layout(demag_plan* p) {
     s.e_off = wb;
     wb += align256(nb * s.parts * sizeof(double));
   }
+  for (Group& G : p->groups) {
+    const Geom& g = G.g;
+    const int P = (int)G.planes.size();
+    const size_t npt = (size_t)g.Kx * g.Ny;
+    G.k_off = kb;
+    kb += align256((size_t)G.npairs() * 6 * npt * sizeof(float2));
+    G.pl_off = kb;
+    kb += align256((size_t)P * sizeof(PlaneInfo));
+    G.t_off = wb;
+    wb += align256(spectrum_elems(g) * sizeof(float2));
+    G.s_off = wb;
+    wb += align256((size_t)3 * P * npt * sizeof(float2));
+    G.e_off = wb;
+    wb += align256((size_t)couple_blocks(g.Kx, g.Ny) * P * sizeof(double));
+  }
   p->kernel_bytes = kb;
   p->work_bytes = wb;
+}
+
+// Coupled group from meshes idx (validated; host only).
+int make_group(const std::vector<int>& idx, const int* dims, const double* cells, const double* origins,
+               const std::vector<long long>& offsets, Group& G) {
+  const char* who = "demag_setup_batch";
+  double fx = 1e300, fy = 1e300, X0 = 1e300, Y0 = 1e300;
+  for (int i : idx) {
+    fx = std::min(fx, cells[3 * i]);
+    fy = std::min(fy, cells[3 * i + 1]);
+    X0 = std::min(X0, origins[3 * i]);
+    Y0 = std::min(Y0, origins[3 * i + 1]);
+  }
+  auto pow2ratio = [](double a, double f, int& s) {
+    const double r = a / f;
+    s = (int)std::lround(r);
+    return s >= 1 && std::fabs(r - s) < 1e-9 * r && (s & (s - 1)) == 0;
+  };
+  auto lattice = [](double d, double f, int& o) {
+    const double r = d / f;
+    o = (int)std::lround(r);
+    return std::fabs(r - o) < 1e-6;
+  };
+  int Lx = 0, Ly = 0;
+  G = Group{};
+  G.members = idx;
+  for (int i : idx) {
+    const int nx = dims[3 * i], ny = dims[3 * i + 1], nz = dims[3 * i + 2];
+    const double dx = cells[3 * i], dy = cells[3 * i + 1], dz = cells[3 * i + 2];
+    if (nx < 1 || ny < 1 || nz < 1 || !(dx > 0 && dy > 0 && dz > 0) || !std::isfinite(dx * dy * dz) ||
+        !std::isfinite(origins[3 * i] + origins[3 * i + 1] + origins[3 * i + 2]))
+      return fail(DEMAG_EINVAL, std::string(who) + ": invalid mesh in a coupled group");
+    int sx, sy, ox, oy;
+    if (!pow2ratio(dx, fx, sx) || !pow2ratio(dy, fy, sy))
+      return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": coupled in-plane cell sizes must be power-of-two multiples");
+    if (!lattice(origins[3 * i] - X0, fx, ox) || !lattice(origins[3 * i + 1] - Y0, fy, oy))
+      return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": coupled origins must lie on the finest in-plane lattice");
+    Lx = std::max(Lx, ox + nx * sx);
+    Ly = std::max(Ly, oy + ny * sy);
+    for (int k = 0; k < nz; ++k) {
+      PlaneInfo pi{};
+      pi.moff = offsets[i];
+      pi.nx = nx; pi.ny = ny; pi.nz = nz; pi.k = k;
+      pi.sx = sx; pi.sy = sy; pi.ox = ox; pi.oy = oy;
+      pi.gid = i;
+      pi.vol = (float)(dx * dy * dz);
+      G.planes.push_back(pi);
+      G.ph.insert(G.ph.end(), {dx, dy, dz});
+      G.pdx.push_back(0.5 * (dx - fx));
+      G.pdy.push_back(0.5 * (dy - fy));
+      G.pz.push_back(origins[3 * i + 2] + (k + 0.5) * dz);
+    }
+  }
+  const int P = (int)G.planes.size();
+  if (P > MAXP) return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": a coupled group has at most 8 z planes");
+  if (Lx < 2 || Lx > 2048 || Ly > 1024)
+    return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": coupled lattice must span 2..2048 x 1..1024 fine cells");
+  Geom& g = G.g;
+  g.nx = Lx; g.ny = Ly; g.nz = P;
+  g.Nx = padded(Lx); g.Ny = padded(Ly); g.Nz = P;
+  g.lnx = ilog2i(g.Nx); g.lny = ilog2i(g.Ny); g.lnz = 0;
+  g.Kx = g.Nx / 2 + 1;
+  g.Kyh = g.Ny > 1 ? g.Ny / 2 + 1 : 1;
+  g.Kzh = 1;
+  g.nTiles = (g.Kx + TILE - 1) / TILE;
+  g.dx = fx; g.dy = fy; g.dz = 1.0;
+  g.yg = 1;
+  g.mid_kw = 4;
+  if ((size_t)P * xrow_pitch_rt(g.lnx) * sizeof(float2) + 8192 > 160 * 1024)
+    return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": coupled planes of one fine row must fit in 160 KiB of LDS");
+  G.fx = fx;
+  G.fy = fy;
+  return DEMAG_OK;
+}
+
+// Pair kernel spectra of a group: FP64 tensor on the padded fine grid, FP64
+// 2D FFT, times -1/(Nx Ny), FP32.
+int build_group(const Group& G, hipStream_t s) {
+  const Geom& g = G.g;
+  const int P = (int)G.planes.size();
+  const size_t cnt = (size_t)g.Nx * g.Ny;
+  GLTable gl{};
+  const int orders[4] = {8, 6, 4, 3};
+  for (int b = 0; b < 4; ++b) {
+    double x[8], w[8];
+    gauss_legendre(orders[b], x, w);
+    gl.n[b] = orders[b];
+    for (int i = 0; i < orders[b]; ++i) {
+      gl.u[b][i] = 0.5 * (1.0 + x[i]);
+      gl.w[b][i] = 0.5 * w[i];
+    }
+  }
+  std::vector<double2> tw(TW_SIZE);
+  for (int k = 0; k < TW_SIZE; ++k) {
+    const double ang = -2.0 * M_PI * k / TW_SIZE;
+    tw[k] = make_double2(std::cos(ang), std::sin(ang));
+  }
+  double2 *buf = nullptr, *d_tw = nullptr;
+  int rc = DEMAG_OK;
+  hipError_t e;
+  do {
+    if (hipMalloc(&buf, 6 * cnt * sizeof(double2)) != hipSuccess || hipMalloc(&d_tw, TW_SIZE * sizeof(double2)) != hipSuccess) {
+      rc = fail(DEMAG_ENOMEM, "demag_bind: set-up temporaries could not be allocated"); break;
+    }
+    if ((e = hipMemcpyAsync(d_tw, tw.data(), TW_SIZE * sizeof(double2), hipMemcpyHostToDevice, s)) != hipSuccess) {
+      rc = fail_hip(e, "twiddle upload"); break;
+    }
+    int pair = 0;
+    for (int p = 0; p < P && rc == DEMAG_OK; ++p) {
+      for (int q = p; q < P; ++q, ++pair) {
+        PairGeom pg{};
+        for (int a = 0; a < 3; ++a) {
+          pg.ht[a] = G.ph[3 * p + a];
+          pg.hs[a] = G.ph[3 * q + a];
+        }
+        pg.fx = G.fx; pg.fy = G.fy;
+        pg.ox = G.pdx[p] - G.pdx[q];
+        pg.oy = G.pdy[p] - G.pdy[q];
+        pg.oz = G.pz[p] - G.pz[q];
+        pg.Nx = g.Nx; pg.Ny = g.Ny; pg.Lx = g.nx; pg.Ly = g.ny;
+        if ((e = launch_pair_tensor(buf, pg, gl, s)) != hipSuccess) { rc = fail_hip(e, "pair tensor"); break; }
+        if ((e = launch_fft64(buf, g.lnx, 1, g.Nx, g.Ny, (long long)cnt, 6 * g.Ny, d_tw, s)) != hipSuccess) {
+          rc = fail_hip(e, "pair x transform"); break;
+        }
+        if (g.Ny > 1 && (e = launch_fft64(buf, g.lny, g.Nx, 1, g.Nx, (long long)cnt, 6 * g.Nx, d_tw, s)) != hipSuccess) {
+          rc = fail_hip(e, "pair y transform"); break;
+        }
+        float2* dst = G.K + (size_t)pair * 6 * g.Kx * g.Ny;
+        if ((e = launch_pair_pack(buf, dst, g.Nx, g.Ny, g.Kx, -1.0 / ((double)g.Nx * g.Ny), s)) != hipSuccess) {
+          rc = fail_hip(e, "pair pack"); break;
+        }
+      }
+    }
+    if (rc == DEMAG_OK && (e = hipStreamSynchronize(s)) != hipSuccess) rc = fail_hip(e, "group set-up");
+  } while (false);
+  if (buf) (void)hipFree(buf);
+  if (d_tw) (void)hipFree(d_tw);
+  return rc;
+}
+
+int run_groups(const demag_plan* p, const float* d_in, const float* ms_mesh, float Ms, float* d_out, unsigned flags,
+               double* d_energy, bool backward, const float* d_H, const double* d_gE, hipStream_t s) {
+  for (const Group& G : p->groups) {
+    const Geom& g = G.g;
+    const int P = (int)G.planes.size();
+    LayerArgs la{G.pl, P, g.ny, g.nTiles, g.Kx, d_in, d_out, G.T, p->tw, ms_mesh, Ms, backward ? 1 : 0,
+                 (flags & DEMAG_ACCUMULATE) ? 1 : 0, d_H, d_gE, -MU0};
+    hipError_t e = launch_layer_x(g.lnx, la, false, s);
+    if (e != hipSuccess) return fail_hip(e, "layer forward pass");
+    MidArgs ma{G.T, nullptr, p->tw, nullptr, g.ny, g.Nz, g.Nx, g.nTiles, g.Kx, g.Kyh, g.Kzh, 2, 1,
+               spectrum_elems(g), g.nTiles * 2 * g.Nz, G.S};
+    if ((e = launch_mid_split(g, ma, 1, s)) != hipSuccess) return fail_hip(e, "layer y pass");
+    CoupleArgs ca{G.S, G.K, G.pl, g.Kx, g.Ny, g.Nx, (d_energy && !backward) ? G.epart : nullptr};
+    if ((e = launch_couple(P, ca, s)) != hipSuccess) return fail_hip(e, "layer coupling");
+    if ((e = launch_mid_split(g, ma, 2, s)) != hipSuccess) return fail_hip(e, "layer inverse y pass");
+    if ((e = launch_layer_x(g.lnx, la, true, s)) != hipSuccess) return fail_hip(e, "layer inverse pass");
+    if (d_energy && !backward) {
+      e = launch_layer_energy(G.epart, couple_blocks(g.Kx, g.Ny), P, G.pl, -0.5 * MU0, d_energy, s);
+      if (e != hipSuccess) return fail_hip(e, "layer energy");
+    }
+  }
+  return DEMAG_OK;
 }
 
 int build_spectrum(const Geom& g, float* d_K, hipStream_t s) {
@@ -339,8 +535,8 @@ int demag_setup(demag_plan** out, int nx, int ny, int nz, double dx, double dy, 
   return DEMAG_OK;
 }
 
-int demag_setup_batch(demag_plan** out, int nmesh, const int* dims, const double* cells, unsigned pbc_flags,
-                      int pbc_images) {
+int demag_setup_batch(demag_plan** out, int nmesh, const int* dims, const double* cells, const double* origins,
+                      const int* groups, unsigned pbc_flags, int pbc_images) {
   (void)pbc_images;
   if (!out) return fail(DEMAG_EINVAL, "demag_setup_batch: out is NULL");
   *out = nullptr;
@@ -351,7 +547,41 @@ int demag_setup_batch(demag_plan** out, int nmesh, const int* dims, const double
   if (!p) return fail(DEMAG_ENOMEM, "demag_setup_batch: out of host memory");
   p->batch = true;
   size_t off = 0;
+  if (groups && !origins) {
+    delete p;
+    return fail(DEMAG_EINVAL, "demag_setup_batch: coupled groups need origins");
+  }
   for (int i = 0; i < nmesh; ++i) {
+    const int nx = dims[3 * i], ny = dims[3 * i + 1], nz = dims[3 * i + 2];
+    if (nx < 1 || ny < 1 || nz < 1) {
+      delete p;
+      return fail(DEMAG_EINVAL, "demag_setup_batch: mesh dimensions must be >= 1");
+    }
+    p->offsets.push_back((long long)off);
+    off += (size_t)3 * nx * ny * nz;
+  }
+  // coupled groups
+  std::vector<bool> coupled(nmesh, false);
+  if (groups) {
+    std::vector<int> ids;
+    for (int i = 0; i < nmesh; ++i)
+      if (groups[i] >= 0 && std::find(ids.begin(), ids.end(), groups[i]) == ids.end()) ids.push_back(groups[i]);
+    for (int id : ids) {
+      std::vector<int> idx;
+      for (int i = 0; i < nmesh; ++i)
+        if (groups[i] == id) idx.push_back(i);
+      Group G;
+      const int rc = make_group(idx, dims, cells, origins, p->offsets, G);
+      if (rc != DEMAG_OK) {
+        delete p;
+        return rc;
+      }
+      for (int i : idx) coupled[i] = true;
+      p->groups.push_back(G);
+    }
+  }
+  for (int i = 0; i < nmesh; ++i) {
+    if (coupled[i]) continue;
     Geom g;
     const int rc = make_geom(dims[3 * i], dims[3 * i + 1], dims[3 * i + 2], cells[3 * i], cells[3 * i + 1],
                              cells[3 * i + 2], g, "demag_setup_batch");
@@ -359,8 +589,6 @@ int demag_setup_batch(demag_plan** out, int nmesh, const int* dims, const double
       delete p;
       return rc;
     }
-    p->offsets.push_back((long long)off);
-    off += (size_t)3 * g.nx * g.ny * g.nz;
     bool placed = false;
     for (Sub& sb : p->subs) {
       const Geom& h = sb.g;
@@ -440,6 +668,18 @@ int demag_bind(demag_plan* p, void* d_kernel, void* d_work, void* stream) {
     if (rc != DEMAG_OK) return rc;
   }
   p->tw = reinterpret_cast<float2*>(kb);
+  for (Group& G : p->groups) {
+    G.K = reinterpret_cast<float2*>(kb + G.k_off);
+    G.pl = reinterpret_cast<PlaneInfo*>(kb + G.pl_off);
+    G.T = reinterpret_cast<float2*>(wb + G.t_off);
+    G.S = reinterpret_cast<float2*>(wb + G.s_off);
+    G.epart = reinterpret_cast<double*>(wb + G.e_off);
+    if ((e = hipMemcpyAsync(G.pl, G.planes.data(), G.planes.size() * sizeof(PlaneInfo), hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
+      return fail_hip(e, "plane table upload");
+    const int rc = build_group(G, s);
+    if (rc != DEMAG_OK) return rc;
+  }
   p->bound = true;
   return DEMAG_OK;
 }
@@ -463,7 +703,10 @@ int demag_field_batch(const demag_plan* p, const float* d_m, const float* d_Ms_m
   if (!d_m || !d_H) return fail(DEMAG_EINVAL, "demag_field_batch: NULL m or H");
   if (flags & ~(unsigned)DEMAG_ACCUMULATE) return fail(DEMAG_EINVAL, "demag_field_batch: unknown flags");
   if (!d_Ms_mesh && !std::isfinite(Ms)) return fail(DEMAG_EINVAL, "demag_field_batch: Ms is not finite");
-  return run_field(p, d_m, nullptr, Ms, d_Ms_mesh, d_H, flags, d_energy, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int rc = run_field(p, d_m, nullptr, Ms, d_Ms_mesh, d_H, flags, d_energy, s);
+  if (rc != DEMAG_OK) return rc;
+  return run_groups(p, d_m, d_Ms_mesh, Ms, d_H, flags, d_energy, false, nullptr, nullptr, s);
 }
 
 int demag_energy(const demag_plan* p, const float* d_m, const float* d_Ms, float Ms, const float* d_H,
@@ -503,7 +746,10 @@ int demag_backward_batch(const demag_plan* p, const float* d_G, const float* d_M
   if (!d_G || !d_grad_m) return fail(DEMAG_EINVAL, "demag_backward_batch: NULL G or grad_m");
   if (d_gE && !d_H) return fail(DEMAG_EINVAL, "demag_backward_batch: the energy term needs the forward field H");
   if (flags & ~(unsigned)DEMAG_ACCUMULATE) return fail(DEMAG_EINVAL, "demag_backward_batch: unknown flags");
-  return run_backward(p, d_G, nullptr, Ms, d_Ms_mesh, d_H, d_gE, d_grad_m, flags, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int rc = run_backward(p, d_G, nullptr, Ms, d_Ms_mesh, d_H, d_gE, d_grad_m, flags, s);
+  if (rc != DEMAG_OK) return rc;
+  return run_groups(p, d_G, d_Ms_mesh, Ms, d_grad_m, flags, nullptr, true, d_H, d_gE, s);
 }
 
 int demag_set_timing_events(demag_plan* p, void* const* events, int count) {

@@ -272,4 +272,12 @@ struct LineShape {
   static constexpr int T = M / R;
 };
 
+__device__ __forceinline__ int xcd_logical(int b, int nblk) {
+  // workgroups are handed to the 8 XCDs round-robin; give each XCD a
+  // contiguous range of logical work so neighbours share its L2
+  const int x = b & 7, idx = b >> 3;
+  const int per = nblk >> 3, rem = nblk & 7;
+  return x * per + min(x, rem) + idx;
+}
+
 }  // namespace demag

@@ -17,16 +17,10 @@
 // only the first N/2 outputs, which is the sum of the two residue inverses.
 #include "fft_core.hpp"
 #include "plan.hpp"
+#include "xrows.hpp"
 
 namespace demag {
 
-__device__ __forceinline__ int xcd_logical(int b, int nblk) {
-  // workgroups are handed to the 8 XCDs round-robin; give each XCD a
-  // contiguous range of logical work so neighbours share its L2
-  const int x = b & 7, idx = b >> 3;
-  const int per = nblk >> 3, rem = nblk & 7;
-  return x * per + min(x, rem) + idx;
-}
 
 // v[z] *= W_NZ^z (forward) or its conjugate, z < NZ/2, as compile-time constants.
 template <int NZ, int Z, bool INV>
@@ -35,20 +29,6 @@ __device__ __forceinline__ void zodd_twiddle(float2 (&v)[NZ / 2]) {
     v[Z] = tw_const<NZ, Z, INV>(v[Z]);
     zodd_twiddle<NZ, Z + 1, INV>(v);
   }
-}
-
-// LDS points reserved for the stage twiddle table of an M-point line FFT
-// (rounded up to 32 points so that the data after it stays 256-byte aligned).
-template <int M>
-constexpr int tab_points() {
-  constexpr int R = LineShape<M>::R;
-  return (M > R) ? ((stage_table_size<M, R>() + 31) / 32) * 32 : 0;
-}
-template <int LNX>
-constexpr int xrow_pitch() { return xrow_pitch_rt(LNX); }
-template <int LNX>
-constexpr int xtab_points() {
-  return (LNX >= 2) ? tab_points<((1 << LNX) / 4 > 0 ? (1 << LNX) / 4 : 1)>() : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -74,7 +54,6 @@ __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_e
   const int tid = threadIdx.x;
   constexpr int L = (NX >= 4) ? NX / 2 : 1;   // packed complex length
   constexpr int PITCH = xrow_pitch<LNX>();    // LDS points per row
-  const float* msrow = nullptr;
   float2* const tab = smem_base;
   float2* const smem = smem_base + xtab_points<LNX>();
 
@@ -86,84 +65,25 @@ __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_e
       smem[row * PITCH] = make_float2(a.m[(size_t)c * nz * ny * nx + off] * ms, 0.f);
     }
   } else {
-    constexpr int P = L / 2;                  // residue sub-FFT length
-    constexpr int R = LineShape<P>::R;
-    constexpr int T = LineShape<P>::T;
-    constexpr int RPR = FWD_THREADS / (2 * T);
-    const int sub = tid / (2 * T);
-    const int r = (tid / T) & 1;
-    const int t = tid % T;
-    fill_stage_table<P, R>(tab, a.tw, tid, FWD_THREADS);
-    const float2 rbase = twiddle<false>(a.tw, t, ilog2(2 * P));
-    __syncthreads();
-    for (int start = 0; start < rows; start += RPR) {
-      const int row = start + sub;
-      const bool act = row < rows;
-      float2* rb = smem + row * PITCH;
-      float2 u[R];
-      if (act) {
-        const int yl = row / nz, z = row - yl * nz;
-        const size_t off = ((size_t)z * ny + (y0 + yl)) * nx;
-        const float* src = a.m + (size_t)c * nz * ny * nx + off;
-        msrow = a.Ms ? a.Ms + off : nullptr;
-        if ((nx & 1) == 0) {
-          // even rows: (x[2m], x[2m+1]) is one aligned float2
-          const float2* s2 = reinterpret_cast<const float2*>(src);
-          const float2* m2 = reinterpret_cast<const float2*>(msrow);
-#pragma unroll
-          for (int j = 0; j < R; ++j) {
-            const int mm = t + T * j;
-            float2 val = make_float2(0.f, 0.f);
-            if (2 * mm < nx) {
-              val = s2[mm];
-              if (m2) {
-                const float2 ms2 = m2[mm];
-                val = make_float2(val.x * ms2.x, val.y * ms2.y);
-              } else {
-                val = make_float2(val.x * a.ms, val.y * a.ms);
-              }
-            }
-            u[j] = val;
-          }
-        } else {
-#pragma unroll
-          for (int j = 0; j < R; ++j) {
-            const int xi = 2 * (t + T * j);
-            float v0 = 0.f, v1 = 0.f;
-            if (xi < nx) v0 = src[xi] * (msrow ? msrow[xi] : a.ms);
-            if (xi + 1 < nx) v1 = src[xi + 1] * (msrow ? msrow[xi + 1] : a.ms);
-            u[j] = make_float2(v0, v1);
-          }
-        }
-        residue_twiddle<R, false>(u, rbase, r != 0);
-        group_fft<P, R, false>(u, rb + r * lds_points<P, R>(), t, tab);
+    const bool even = (nx & 1) == 0;
+    xfwd_rows<LNX, FWD_THREADS>(smem, tab, a.tw, rows, PITCH, [&](int row, int mm) -> float2 {
+      const int yl = row / nz, z = row - yl * nz;
+      const size_t off = ((size_t)z * ny + (y0 + yl)) * nx;
+      const float* src = a.m + (size_t)c * nz * ny * nx + off;
+      const float* msr = a.Ms ? a.Ms + off : nullptr;
+      const int xi = 2 * mm;
+      if (even) {
+        // even rows: (x[2m], x[2m+1]) is one aligned float2
+        if (xi >= nx) return make_float2(0.f, 0.f);
+        const float2 v = reinterpret_cast<const float2*>(src)[mm];
+        const float2 s2 = msr ? reinterpret_cast<const float2*>(msr)[mm] : make_float2(a.ms, a.ms);
+        return make_float2(v.x * s2.x, v.y * s2.y);
       }
-      __syncthreads();
-      if (act) {
-#pragma unroll
-        for (int j = 0; j < R; ++j) rb[2 * (t + T * j) + r] = u[j];
-      }
-      __syncthreads();
-      if (act) {
-        // X[k] = E + W^k O and X[L-k] = conj(E - W^k O), with
-        // E = (U[k] + conj U[L-k]) / 2 and O = -i (U[k] - conj U[L-k]) / 2.
-        for (int k = tid % (2 * T); k <= L / 2; k += 2 * T) {
-          const float2 Uk = rb[k];
-          const float2 Um = rb[(L - k) & (L - 1)];
-          const float2 E = make_float2(0.5f * (Uk.x + Um.x), 0.5f * (Uk.y - Um.y));
-          const float2 O = make_float2(0.5f * (Uk.y + Um.y), -0.5f * (Uk.x - Um.x));
-          const float2 WO = cmul(O, twiddle<false>(a.tw, k, LNX));
-          if (k == 0) {
-            rb[0] = make_float2(E.x + O.x, E.y + O.y);
-            rb[L] = make_float2(E.x - O.x, E.y - O.y);
-          } else {
-            rb[k] = cadd(E, WO);
-            if (k != L - k) rb[L - k] = cconj(csub(E, WO));
-          }
-        }
-      }
-      __syncthreads();
-    }
+      float v0 = 0.f, v1 = 0.f;
+      if (xi < nx) v0 = src[xi] * (msr ? msr[xi] : a.ms);
+      if (xi + 1 < nx) v1 = src[xi + 1] * (msr ? msr[xi + 1] : a.ms);
+      return make_float2(v0, v1);
+    });
   }
   __syncthreads();
 
@@ -233,7 +153,11 @@ __device__ __forceinline__ Tv block_sum(Tv v, Tv* red) {
   return s;
 }
 
-template <int LNY, int KW, bool ENERGY>
+// MODE 0: y FFT, kernel product, inverse y FFT (the pipelined pass).
+// MODE 1: y FFT only; spectra to S[c][kz][kx][ky] with ky ordered by residue
+//         (r * NY/2 + k' for ky = 2k' + r).
+// MODE 2: inverse y FFT only, from S.
+template <int LNY, int KW, bool ENERGY, int MODE = 0>
 __global__ void __launch_bounds__(mid_threads(LNY, KW)) __attribute__((amdgpu_waves_per_eu(LNY >= 11 ? 2 : 4, 8)))
 k_mid(MidArgs a) {
   constexpr int NY = 1 << LNY;
@@ -257,7 +181,7 @@ k_mid(MidArgs a) {
   const int half = lg % halves;
   const int kzi = (lg / halves) % a.Nz;
   const int tile = lg / (halves * a.Nz);
-  const int kz = kz_of(kzi, a.Nz);
+  const int kz = MODE == 0 ? kz_of(kzi, a.Nz) : kzi;
   const int ny = a.ny;
 
   const int tid = threadIdx.x;
@@ -278,38 +202,59 @@ k_mid(MidArgs a) {
 
   if constexpr (M > R) fill_stage_table<M, R>(tab, a.tw, tid, blockDim.x);
   const float2 rbase = twiddle<false>(a.tw, t, ilog2(2 * M));
+  __syncthreads();   // stage table complete before any FFT reads it
   float2 v[3][R];
+  // S index of (c, kz, kx, residue r, k') in MODE 1 / 2
+  auto sidx = [&](int c, int j) -> size_t {
+    return (((size_t)c * a.Nz + kz) * a.Kx + kx) * NY + (size_t)r * M + (t + T * j);
+  };
+  if constexpr (MODE == 2) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    float2* blk = blk0 + c * cstride;
-    __syncthreads();
-    {
-      // 16-byte copies: KW/2 float4 per y row of the half tile
-      constexpr int V = KW / 2;
-      float4* st4 = reinterpret_cast<float4*>(stage);
-      const float4* b4 = reinterpret_cast<const float4*>(blk);
-      for (int e = tid; e < ny * V; e += blockDim.x) {
-        const int y = e / V, q = e - y * V;
-        st4[e] = b4[(unsigned)y * (TILE / 2) + q];
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < R; ++j) v[c][j] = valid ? a.S[sidx(c, j)] : make_float2(0.f, 0.f);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float2* blk = blk0 + c * cstride;
+      __syncthreads();
+      {
+        // 16-byte copies: KW/2 float4 per y row of the half tile
+        constexpr int V = KW / 2;
+        float4* st4 = reinterpret_cast<float4*>(stage);
+        const float4* b4 = reinterpret_cast<const float4*>(blk);
+        for (int e = tid; e < ny * V; e += blockDim.x) {
+          const int y = e / V, q = e - y * V;
+          st4[e] = b4[(unsigned)y * (TILE / 2) + q];
+        }
       }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int y = t + T * j;
+        v[c][j] = (valid && y < ny) ? stage[y * KW + w] : make_float2(0.f, 0.f);
+      }
+      if constexpr (NRES == 2) residue_twiddle<R, false>(v[c], rbase, r != 0);
     }
     __syncthreads();
+    if (lane_act) {
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const int y = t + T * j;
-      v[c][j] = (valid && y < ny) ? stage[y * KW + w] : make_float2(0.f, 0.f);
+      for (int c = 0; c < 3; ++c) group_fft<M, R, false>(v[c], scr, t, tab);
     }
-    if constexpr (NRES == 2) residue_twiddle<R, false>(v[c], rbase, r != 0);
-  }
-  __syncthreads();
-  if (lane_act) {
+    if constexpr (MODE == 1) {
+      if (valid) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) group_fft<M, R, false>(v[c], scr, t, tab);
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int j = 0; j < R; ++j) a.S[sidx(c, j)] = v[c][j];
+      }
+      return;
+    }
   }
 
   // point-wise product with the real, symmetric kernel spectrum
   double e = 0.0;
-  if (lane_act) {
+  if (lane_act && MODE == 0) {
     const int kzf = (kz <= a.Nz / 2) ? kz : a.Nz - kz;
     const float sz = (kz <= a.Nz / 2) ? 1.f : -1.f;
     const int kxc = min(kx, a.Kx - 1);
@@ -337,6 +282,8 @@ k_mid(MidArgs a) {
       v[0][j] = hx; v[1][j] = hy; v[2][j] = hz;
     }
     if (ENERGY && valid) e = (double)(wkx * ef);
+  }
+  if (lane_act) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       group_fft<M, R, true>(v[c], scr, t, tab);
@@ -459,69 +406,22 @@ __global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_e
       dst[0] = a.accumulate ? dst[0] + val : val;
     }
   } else {
-    constexpr int P = L / 2;
-    constexpr int R = LineShape<P>::R;
-    constexpr int T = LineShape<P>::T;
-    constexpr int RPR = INV_THREADS / (2 * T);
-    const int sub = tid / (2 * T);
-    const int r = (tid / T) & 1;
-    const int t = tid % T;
-    fill_stage_table<P, R>(tab, a.tw, tid, INV_THREADS);
-    const float2 rbase = twiddle<false>(a.tw, t, ilog2(2 * P));
-    __syncthreads();
     const float beta = (a.scale_out && a.beta_ptr) ? (float)(a.beta_scale * *a.beta_ptr) : 0.f;
-    for (int start = 0; start < rows; start += RPR) {
-      const int row = start + sub;
-      const bool act = row < rows;
-      float2* rb = smem + row * PITCH;
-      float2 u[R];
-      if (act) {
-        // U[k] = (X[k] + conj X[L-k]) + i W^-k (X[k] - conj X[L-k]); inverse
-        // of the packed FFT of (x[2m], x[2m+1]), scaled to match X
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-          const int k = 2 * (t + T * j) + r;
-          const float2 Xk = rb[k];
-          const float2 Xm = rb[L - k];
-          const float2 S = make_float2(Xk.x + Xm.x, Xk.y - Xm.y);
-          const float2 D = make_float2(Xk.x - Xm.x, Xk.y + Xm.y);
-          const float2 WD = cmul(D, twiddle<true>(a.tw, k, LNX));
-          u[j] = make_float2(S.x - WD.y, S.y + WD.x);
-        }
+    xinv_rows<LNX, INV_THREADS>(smem, tab, a.tw, rows, PITCH, [&](int row, int mm, float2 uu) {
+      const int yl = row / nz, z = row - yl * nz;
+      const size_t off = ((size_t)z * ny + (y0 + yl)) * nx;
+      float* dst = a.H + cbase + off;
+      const int xi = 2 * mm;
+      float v0 = uu.x, v1 = uu.y;
+      if (a.scale_out) {
+        const float* aux = a.aux + cbase + off;
+        const float* msr = a.Ms ? a.Ms + off : nullptr;
+        if (xi < nx) v0 = (msr ? msr[xi] : a.ms) * (v0 + (a.beta_ptr ? beta * aux[xi] : 0.f));
+        if (xi + 1 < nx) v1 = (msr ? msr[xi + 1] : a.ms) * (v1 + (a.beta_ptr ? beta * aux[xi + 1] : 0.f));
       }
-      __syncthreads();
-      if (act) {
-        group_fft<P, R, true>(u, rb + r * lds_points<P, R>(), t, tab);
-        residue_twiddle<R, true>(u, rbase, r != 0);
-      }
-      __syncthreads();
-      if (act && r == 1) {
-#pragma unroll
-        for (int j = 0; j < R; ++j) rb[t + T * j] = u[j];
-      }
-      __syncthreads();
-      if (act && r == 0) {
-        const int yl = row / nz, z = row - yl * nz;
-        const size_t off = ((size_t)z * ny + (y0 + yl)) * nx;
-        float* dst = a.H + cbase + off;
-        const float* aux = a.scale_out ? a.aux + cbase + off : nullptr;
-        const float* msr = (a.scale_out && a.Ms) ? a.Ms + off : nullptr;
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-          const int mm = t + T * j;
-          const float2 uu = cadd(u[j], rb[mm]);
-          const int xi = 2 * mm;
-          float v0 = uu.x, v1 = uu.y;
-          if (a.scale_out) {
-            if (xi < nx) v0 = (msr ? msr[xi] : a.ms) * (v0 + (a.beta_ptr ? beta * aux[xi] : 0.f));
-            if (xi + 1 < nx) v1 = (msr ? msr[xi + 1] : a.ms) * (v1 + (a.beta_ptr ? beta * aux[xi + 1] : 0.f));
-          }
-          if (xi < nx) dst[xi] = a.accumulate ? dst[xi] + v0 : v0;
-          if (xi + 1 < nx) dst[xi + 1] = a.accumulate ? dst[xi + 1] + v1 : v1;
-        }
-      }
-      __syncthreads();
-    }
+      if (xi < nx) dst[xi] = a.accumulate ? dst[xi] + v0 : v0;
+      if (xi + 1 < nx) dst[xi + 1] = a.accumulate ? dst[xi + 1] + v1 : v1;
+    });
   }
 }
 
@@ -680,6 +580,45 @@ hipError_t launch_mid(const Geom& g, const MidArgs& a, hipStream_t s) {
     case 9: return mid_kw_switch<9>(g, a, s);
     case 10: return mid_kw_switch<10>(g, a, s);
     case 11: return mid_kw_switch<11>(g, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int LNY, int MODE>
+static hipError_t mid_split_one(const Geom& g, const MidArgs& a, hipStream_t s) {
+  constexpr int NY = 1 << LNY;
+  constexpr int M = NY > 1 ? NY / 2 : 1;
+  constexpr int NRES = NY > 1 ? 2 : 1;
+  size_t lds = (size_t)NRES * 4 * lds_points<M, LineShape<M>::R>() * sizeof(float2);
+  const size_t st = (size_t)g.ny * 4 * sizeof(float2);
+  if (st > lds) lds = st;
+  lds += tab_points<M>() * sizeof(float2);
+  hipError_t e = prep_lds(k_mid<LNY, 4, false, MODE>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_mid<LNY, 4, false, MODE>), dim3(g.nTiles * 2 * g.Nz * a.nb), dim3(mid_threads(LNY, 4)), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int LNY>
+static hipError_t mid_split_mode(const Geom& g, const MidArgs& a, int mode, hipStream_t s) {
+  return mode == 1 ? mid_split_one<LNY, 1>(g, a, s) : mid_split_one<LNY, 2>(g, a, s);
+}
+
+// y passes without the kernel product (coupled layers): mode 1 forward into
+// S, mode 2 inverse from S; 4 kx per workgroup
+hipError_t launch_mid_split(const Geom& g, const MidArgs& a, int mode, hipStream_t s) {
+  switch (g.lny) {
+    case 0: return mid_split_mode<0>(g, a, mode, s);
+    case 2: return mid_split_mode<2>(g, a, mode, s);
+    case 3: return mid_split_mode<3>(g, a, mode, s);
+    case 4: return mid_split_mode<4>(g, a, mode, s);
+    case 5: return mid_split_mode<5>(g, a, mode, s);
+    case 6: return mid_split_mode<6>(g, a, mode, s);
+    case 7: return mid_split_mode<7>(g, a, mode, s);
+    case 8: return mid_split_mode<8>(g, a, mode, s);
+    case 9: return mid_split_mode<9>(g, a, mode, s);
+    case 10: return mid_split_mode<10>(g, a, mode, s);
+    case 11: return mid_split_mode<11>(g, a, mode, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -1,0 +1,265 @@
+// Coupled layers (Sec. 3, Eq. 4): meshes with their own cell sizes and
+// positions whose fields couple through inter-mesh tensors N(r, h_k, h_i);
+// "the summation of inter-mesh contributions moved to the transform space".
+//
+// All z planes of a group share one fine in-plane lattice (coarser layers
+// are zero-inserted at their stride).  Per evaluation:
+//   k_lfwd   : per (fine row, component): real-to-complex x FFT of every
+//              plane's row (zeros where a plane has no cell) -> T
+//   k_mid<1> : y FFT of every (plane, kx) line -> S (full ky range)
+//   k_couple : per (kx, ky): H_p = sum_q K_pq M_q over all plane pairs, the
+//              pair kernels of q > p from p < q by reciprocity
+//              (V_p N_pq(r) = V_q N_qp(-r) -> K_qp = V_p/V_q conj K_pq);
+//              Parseval energy partials
+//   k_mid<2> : inverse y FFT -> T
+//   k_linv   : inverse x FFT, keeping each plane's own cells -> H
+#include "fft_core.hpp"
+#include "plan.hpp"
+#include "xrows.hpp"
+#include "launch.hpp"
+
+namespace demag {
+
+template <int LNX>
+__global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8))) k_lfwd(LayerArgs a) {
+  extern __shared__ float2 smem_base[];
+  constexpr int PITCH = xrow_pitch<LNX>();
+  float2* const tab = smem_base;
+  float2* const smem = smem_base + xtab_points<LNX>();
+  const int lg = xcd_logical(blockIdx.x, gridDim.x);
+  const int c = lg / a.Ly, v = lg - c * a.Ly;
+  xfwd_rows<LNX, FWD_THREADS>(smem, tab, a.tw, a.P, PITCH, [&](int p, int mm) -> float2 {
+    const PlaneInfo pi = a.pl[p];
+    const int jy = v - pi.oy;
+    if (jy < 0 || jy % pi.sy != 0 || jy / pi.sy >= pi.ny) return make_float2(0.f, 0.f);
+    const float* src = a.m + pi.moff + (((size_t)c * pi.nz + pi.k) * pi.ny + jy / pi.sy) * pi.nx;
+    const float sc = a.backward ? 1.0f / pi.vol : (a.ms_mesh ? a.ms_mesh[pi.gid] : a.ms);
+    float val[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int ix = 2 * mm + h - pi.ox;
+      val[h] = (ix >= 0 && ix % pi.sx == 0 && ix / pi.sx < pi.nx) ? sc * src[ix / pi.sx] : 0.f;
+    }
+    return make_float2(val[0], val[1]);
+  });
+  const int Kx = a.Kx;
+  for (int it = threadIdx.x; it < a.P * Kx; it += FWD_THREADS) {
+    const int p = it / Kx, kx = it - p * Kx;
+    a.T[((((size_t)c * a.P + p) * a.nTiles + kx / TILE) * a.Ly + v) * TILE + (kx % TILE)] = smem[p * PITCH + kx];
+  }
+}
+
+template <int LNX>
+__global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8))) k_linv(LayerArgs a) {
+  extern __shared__ float2 smem_base[];
+  constexpr int PITCH = xrow_pitch<LNX>();
+  float2* const tab = smem_base;
+  float2* const smem = smem_base + xtab_points<LNX>();
+  const int lg = xcd_logical(blockIdx.x, gridDim.x);
+  const int c = lg / a.Ly, v = lg - c * a.Ly;
+  const int Kx = a.Kx;
+  for (int it = threadIdx.x; it < a.P * Kx; it += INV_THREADS) {
+    const int p = it / Kx, kx = it - p * Kx;
+    smem[p * PITCH + kx] = a.T[((((size_t)c * a.P + p) * a.nTiles + kx / TILE) * a.Ly + v) * TILE + (kx % TILE)];
+  }
+  __syncthreads();
+  xinv_rows<LNX, INV_THREADS>(smem, tab, a.tw, a.P, PITCH, [&](int p, int mm, float2 uu) {
+    const PlaneInfo pi = a.pl[p];
+    const int jy = v - pi.oy;
+    if (jy < 0 || jy % pi.sy != 0 || jy / pi.sy >= pi.ny) return;
+    const size_t row = pi.moff + (((size_t)c * pi.nz + pi.k) * pi.ny + jy / pi.sy) * pi.nx;
+    float post = 1.f, beta = 0.f;
+    if (a.backward) {
+      post = (a.ms_mesh ? a.ms_mesh[pi.gid] : a.ms) * pi.vol;
+      if (a.beta_ptr) beta = (float)(a.beta_scale * a.beta_ptr[pi.gid]);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int ix = 2 * mm + h - pi.ox;
+      if (ix >= 0 && ix % pi.sx == 0 && ix / pi.sx < pi.nx) {
+        const size_t o = row + ix / pi.sx;
+        float val = h ? uu.y : uu.x;
+        if (a.backward) val = post * (val + (a.beta_ptr ? beta * a.aux[o] : 0.f));
+        a.H[o] = a.accumulate ? a.H[o] + val : val;
+      }
+    }
+  });
+}
+
+// complex 3x3 symmetric K (xx yy zz xy xz yz) times complex vector, added to h
+__device__ __forceinline__ void sym_mac(float2 (&h)[3], const float2 (&k)[6], const float2 (&m)[3], float s,
+                                       bool conj_k) {
+  auto mul = [&](float2 kk, float2 mm) {
+    const float2 kc = conj_k ? cconj(kk) : kk;
+    return cscale(cmul(kc, mm), s);
+  };
+  h[0] = cadd(h[0], cadd(mul(k[0], m[0]), cadd(mul(k[3], m[1]), mul(k[4], m[2]))));
+  h[1] = cadd(h[1], cadd(mul(k[3], m[0]), cadd(mul(k[1], m[1]), mul(k[5], m[2]))));
+  h[2] = cadd(h[2], cadd(mul(k[4], m[0]), cadd(mul(k[5], m[1]), mul(k[2], m[2]))));
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_couple(CoupleArgs a) {
+  __shared__ double red[4][P];
+  const size_t npt = (size_t)a.Kx * a.NY;
+  const size_t pt = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const bool act = pt < npt;
+  const int kx = act ? (int)(pt / a.NY) : 0;
+  float2 M[P][3], H[P][3];
+  float vol[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    vol[p] = a.pl[p].vol;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      M[p][c] = act ? a.S[((size_t)c * P + p) * npt + pt] : make_float2(0.f, 0.f);
+      H[p][c] = make_float2(0.f, 0.f);
+    }
+  }
+  int pair = 0;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+#pragma unroll
+    for (int q = p; q < P; ++q) {
+      float2 k6[6];
+#pragma unroll
+      for (int e = 0; e < 6; ++e) k6[e] = act ? a.K[((size_t)pair * 6 + e) * npt + pt] : make_float2(0.f, 0.f);
+      sym_mac(H[p], k6, M[q], 1.f, false);
+      if (q != p) sym_mac(H[q], k6, M[p], vol[p] / vol[q], true);
+      ++pair;
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.S[((size_t)c * P + p) * npt + pt] = H[p][c];
+  }
+  if (a.epart) {
+    const float w = (kx == 0 || 2 * kx == a.Nx) ? 1.f : 2.f;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      double e = 0.0;
+      if (act) {
+        float d = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) d += M[p][c].x * H[p][c].x + M[p][c].y * H[p][c].y;
+        e = (double)(w * vol[p] * d);
+      }
+      for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o);
+      if (lane == 0) red[wv][p] = e;
+    }
+    __syncthreads();
+    if (threadIdx.x < P) {
+      const double s = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+      a.epart[(size_t)blockIdx.x * P + threadIdx.x] = s;
+    }
+  }
+}
+
+// energies of the meshes of a group: out[gid] = scale * sum over the mesh's
+// planes and all workgroups' partials (fixed order)
+__global__ void __launch_bounds__(RED_THREADS) k_lenergy(const double* part, int nblk, int P, const PlaneInfo* pl,
+                                                         double scale, double* out) {
+  __shared__ double red[RED_THREADS / 64];
+  __shared__ double tot[MAXP];
+  for (int p = 0; p < P; ++p) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += RED_THREADS) s += part[(size_t)i * P + p];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < RED_THREADS / 64; ++w) t += red[w];
+      tot[p] = t;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int p = 0; p < P; ++p) {
+      bool first = true;
+      for (int q = 0; q < p; ++q) first = first && pl[q].gid != pl[p].gid;
+      if (!first) continue;
+      double t = 0.0;
+      for (int q = p; q < P; ++q)
+        if (pl[q].gid == pl[p].gid) t += tot[q];
+      out[pl[p].gid] = scale * t;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename K>
+static hipError_t prep(K kern, size_t lds) {
+  if (lds > 65536)
+    return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return hipSuccess;
+}
+
+template <int LNX>
+static hipError_t lx_one(const LayerArgs& a, bool inverse, hipStream_t s) {
+  const size_t lds = ((size_t)a.P * xrow_pitch<LNX>() + xtab_points<LNX>()) * sizeof(float2);
+  dim3 grid(a.Ly * 3);
+  if (inverse) {
+    hipError_t e = prep(k_linv<LNX>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_linv<LNX>), grid, dim3(INV_THREADS), lds, s, a);
+  } else {
+    hipError_t e = prep(k_lfwd<LNX>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_lfwd<LNX>), grid, dim3(FWD_THREADS), lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_layer_x(int lnx, const LayerArgs& a, bool inverse, hipStream_t s) {
+  switch (lnx) {
+    case 2: return lx_one<2>(a, inverse, s);
+    case 3: return lx_one<3>(a, inverse, s);
+    case 4: return lx_one<4>(a, inverse, s);
+    case 5: return lx_one<5>(a, inverse, s);
+    case 6: return lx_one<6>(a, inverse, s);
+    case 7: return lx_one<7>(a, inverse, s);
+    case 8: return lx_one<8>(a, inverse, s);
+    case 9: return lx_one<9>(a, inverse, s);
+    case 10: return lx_one<10>(a, inverse, s);
+    case 11: return lx_one<11>(a, inverse, s);
+    case 12: return lx_one<12>(a, inverse, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int couple_blocks(int Kx, int NY) { return (int)(((size_t)Kx * NY + 255) / 256); }
+
+template <int P>
+static hipError_t couple_one(const CoupleArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_couple<P>), dim3(couple_blocks(a.Kx, a.NY)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_couple(int P, const CoupleArgs& a, hipStream_t s) {
+  switch (P) {
+    case 1: return couple_one<1>(a, s);
+    case 2: return couple_one<2>(a, s);
+    case 3: return couple_one<3>(a, s);
+    case 4: return couple_one<4>(a, s);
+    case 5: return couple_one<5>(a, s);
+    case 6: return couple_one<6>(a, s);
+    case 7: return couple_one<7>(a, s);
+    case 8: return couple_one<8>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_layer_energy(const double* part, int nblk, int P, const PlaneInfo* pl, double scale, double* out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_lenergy, dim3(1), dim3(RED_THREADS), 0, s, part, nblk, P, pl, scale, out);
+  return hipGetLastError();
+}
+
+}  // namespace demag

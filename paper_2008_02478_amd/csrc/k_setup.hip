@@ -16,6 +16,7 @@
 //               from (-i)^2) and store FP32 in the layout read by the middle
 //               pass, K[kz][kx][component][ky].
 #include <hip/hip_runtime.h>
+#include <climits>
 #include "plan.hpp"
 
 namespace demag {
@@ -167,6 +168,156 @@ __global__ void k_pack(const double* __restrict__ in, float* __restrict__ K, int
 
 }  // namespace demag
 
+namespace demag {
+
+// ---------------------------------------------------------------------------
+// Inter-mesh tensor between cells of different sizes (Sec. 3, Eq. 4:
+// N(r, h_k, h_i)).  Closed form: f/g under a 4-point stencil per axis,
+// X +- (a+b)/2 weight -1 and X +- (a-b)/2 weight +1 (a target, b source
+// size), over 4 pi V_target.  Far field: Gauss-Legendre quadrature of the
+// dipole kernel against the overlap weight of the two boxes per axis, a
+// trapezoid of base a + b and plateau min(a, b).
+// ---------------------------------------------------------------------------
+template <bool OFFDIAG>
+__device__ double stencil64(double X, double Y, double Z, double ta, double sa, double tb, double sb, double tc,
+                            double sc) {
+  const double ox[4] = {0.5 * (ta + sa), -0.5 * (ta + sa), 0.5 * (ta - sa), -0.5 * (ta - sa)};
+  const double oy[4] = {0.5 * (tb + sb), -0.5 * (tb + sb), 0.5 * (tb - sb), -0.5 * (tb - sb)};
+  const double oz[4] = {0.5 * (tc + sc), -0.5 * (tc + sc), 0.5 * (tc - sc), -0.5 * (tc - sc)};
+  double acc = 0.0;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
+      for (int k = 0; k < 4; ++k) {
+        const double w = (i < 2 ? -1.0 : 1.0) * (j < 2 ? -1.0 : 1.0) * (k < 2 ? -1.0 : 1.0);
+        acc += w * (OFFDIAG ? ng(X + ox[i], Y + oy[j], Z + oz[k]) : nf(X + ox[i], Y + oy[j], Z + oz[k]));
+      }
+  return acc / (4.0 * M_PI * ta * tb * tc);
+}
+
+// idx-th quadrature node of the overlap weight of widths a and b along one
+// axis (3 pieces of n nodes: two ramps, then the plateau when a != b)
+__device__ bool trap_node(double a, double b, int n, int idx, const GLTable& gl, int band, double& u, double& w) {
+  const double lo = 0.5 * fabs(a - b), hi = 0.5 * (a + b);
+  const int piece = idx / n, i = idx - piece * n;
+  const double x = gl.u[band][i], wx = gl.w[band][i];
+  if (piece < 2) {
+    const double v = lo + (hi - lo) * x;
+    u = piece == 0 ? v : -v;
+    w = (hi - lo) * wx * (hi - v);
+    return true;
+  }
+  if (lo <= 0.0) return false;
+  u = -lo + 2.0 * lo * x;
+  w = 2.0 * lo * wx * fmin(a, b);
+  return true;
+}
+
+__device__ void tensor_unequal_dev(double X, double Y, double Z, const double* ht, const double* hs,
+                                   const GLTable& gl, double* N) {
+  const double hmax = fmax(fmax(fmax(ht[0], ht[1]), ht[2]), fmax(fmax(hs[0], hs[1]), hs[2]));
+  const double dist = sqrt(X * X + Y * Y + Z * Z) / hmax;
+  if (dist < 3.0) {
+    N[0] = stencil64<false>(X, Y, Z, ht[0], hs[0], ht[1], hs[1], ht[2], hs[2]);
+    N[1] = stencil64<false>(Y, X, Z, ht[1], hs[1], ht[0], hs[0], ht[2], hs[2]);
+    N[2] = stencil64<false>(Z, Y, X, ht[2], hs[2], ht[1], hs[1], ht[0], hs[0]);
+    N[3] = stencil64<true>(X, Y, Z, ht[0], hs[0], ht[1], hs[1], ht[2], hs[2]);
+    N[4] = stencil64<true>(X, Z, Y, ht[0], hs[0], ht[2], hs[2], ht[1], hs[1]);
+    N[5] = stencil64<true>(Y, Z, X, ht[1], hs[1], ht[2], hs[2], ht[0], hs[0]);
+    return;
+  }
+  const int band = dist < 6.0 ? 0 : dist < 16.0 ? 1 : dist < 40.0 ? 2 : 3;
+  const int n = gl.n[band];
+  for (int q = 0; q < 6; ++q) N[q] = 0.0;
+  for (int ia = 0; ia < 3 * n; ++ia) {
+    double ux, wx;
+    if (!trap_node(ht[0], hs[0], n, ia, gl, band, ux, wx)) continue;
+    const double vx = X + ux;
+    for (int ib = 0; ib < 3 * n; ++ib) {
+      double uy, wy;
+      if (!trap_node(ht[1], hs[1], n, ib, gl, band, uy, wy)) continue;
+      const double vy = Y + uy;
+      for (int ic = 0; ic < 3 * n; ++ic) {
+        double uz, wz;
+        if (!trap_node(ht[2], hs[2], n, ic, gl, band, uz, wz)) continue;
+        const double vz = Z + uz;
+        const double r2 = vx * vx + vy * vy + vz * vz;
+        const double wt = wx * wy * wz / (r2 * r2 * sqrt(r2));
+        N[0] += wt * (r2 - 3.0 * vx * vx);
+        N[1] += wt * (r2 - 3.0 * vy * vy);
+        N[2] += wt * (r2 - 3.0 * vz * vz);
+        N[3] -= wt * 3.0 * vx * vy;
+        N[4] -= wt * 3.0 * vx * vz;
+        N[5] -= wt * 3.0 * vy * vz;
+      }
+    }
+  }
+  const double s = 1.0 / (4.0 * M_PI * ht[0] * ht[1] * ht[2]);
+  for (int q = 0; q < 6; ++q) N[q] *= s;
+}
+
+// One plane pair on the padded fine grid [6][Ny][Nx] (FP64 complex, imaginary
+// part 0): lattice offset u = i for i < Lx, i - Nx for i > Nx - Lx, none
+// (zero) in between; the same along y.
+__global__ void k_pair_tensor(double2* __restrict__ out, PairGeom pg, GLTable gl) {
+  const size_t cnt = (size_t)pg.Nx * pg.Ny;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= cnt) return;
+  const int i = (int)(idx % pg.Nx), j = (int)(idx / pg.Nx);
+  const int u = i < pg.Lx ? i : (i > pg.Nx - pg.Lx ? i - pg.Nx : INT_MIN);
+  const int v = j < pg.Ly ? j : (j > pg.Ny - pg.Ly ? j - pg.Ny : INT_MIN);
+  double N[6] = {0, 0, 0, 0, 0, 0};
+  if (u != INT_MIN && v != INT_MIN)
+    tensor_unequal_dev(u * pg.fx + pg.ox, v * pg.fy + pg.oy, pg.oz, pg.ht, pg.hs, gl, N);
+  for (int q = 0; q < 6; ++q) out[q * cnt + idx] = make_double2(N[q], 0.0);
+}
+
+// In-place FP64 FFT of lines of N = 2^logN points (radix 2, in LDS).  Line l
+// starts at (l / lpb) * bstride + (l % lpb) * ls, elements es apart.
+__global__ void k_fft64_lines(double2* __restrict__ data, int logN, long long es, long long ls, int lpb,
+                              long long bstride, const double2* __restrict__ tw64) {
+  extern __shared__ double2 buf[];
+  const int N = 1 << logN;
+  const int l = blockIdx.x;
+  double2* base = data + (long long)(l / lpb) * bstride + (long long)(l % lpb) * ls;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    int r = 0, x = i;
+    for (int b = 0; b < logN; ++b) { r = (r << 1) | (x & 1); x >>= 1; }
+    buf[r] = base[(long long)i * es];
+  }
+  __syncthreads();
+  for (int len = 2; len <= N; len <<= 1) {
+    const int half = len >> 1, step = 4096 / len;
+    for (int k = threadIdx.x; k < N / 2; k += blockDim.x) {
+      const int j = k % half, s0 = (k / half) * len;
+      const double2 w = tw64[j * step];
+      const double2 a = buf[s0 + j], b = buf[s0 + j + half];
+      const double2 bw = make_double2(b.x * w.x - b.y * w.y, b.x * w.y + b.y * w.x);
+      buf[s0 + j] = make_double2(a.x + bw.x, a.y + bw.y);
+      buf[s0 + j + half] = make_double2(a.x - bw.x, a.y - bw.y);
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < N; i += blockDim.x) base[(long long)i * es] = buf[i];
+}
+
+// [6][Ny][Nx] FP64 spectrum -> one pair's block K[6][Kx][NY] (FP32 complex)
+// times scale, ky stored by residue (r * NY/2 + k' for ky = 2k' + r).
+__global__ void k_pair_pack(const double2* __restrict__ in, float2* __restrict__ K, int Nx, int Ny, int Kx,
+                            double scale) {
+  const size_t tot = (size_t)6 * Kx * Ny;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= tot) return;
+  const int ry = (int)(idx % Ny);
+  const int kx = (int)((idx / Ny) % Kx);
+  const int c = (int)(idx / ((size_t)Ny * Kx));
+  const int M = Ny > 1 ? Ny / 2 : 1;
+  const int ky = Ny > 1 ? 2 * (ry % M) + ry / M : 0;
+  const double2 v = in[(size_t)c * Nx * Ny + (size_t)ky * Nx + kx];
+  K[idx] = make_float2((float)(scale * v.x), (float)(scale * v.y));
+}
+
+}  // namespace demag
+
 #include "launch.hpp"
 
 namespace demag {
@@ -190,6 +341,33 @@ hipError_t launch_pack(const double* in, float* K, const Geom& g, hipStream_t s)
   const size_t tot = (size_t)6 * g.Kzh * g.Kyh * g.Kx;
   hipLaunchKernelGGL(k_pack, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, in, K, g.Kx, g.Kyh, g.Kzh,
                      1.0 / ((double)g.Nx * g.Ny * g.Nz));
+  return hipGetLastError();
+}
+
+}  // namespace demag
+
+namespace demag {
+
+hipError_t launch_pair_tensor(double2* out, const PairGeom& pg, const GLTable& gl, hipStream_t s) {
+  const size_t cnt = (size_t)pg.Nx * pg.Ny;
+  hipLaunchKernelGGL(k_pair_tensor, dim3((unsigned)((cnt + 127) / 128)), dim3(128), 0, s, out, pg, gl);
+  return hipGetLastError();
+}
+
+hipError_t launch_fft64(double2* data, int logN, long long es, long long ls, int lpb, long long bstride, int nlines,
+                        const double2* tw64, hipStream_t s) {
+  const size_t lds = (size_t)sizeof(double2) << logN;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_fft64_lines, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_fft64_lines, dim3(nlines), dim3(256), lds, s, data, logN, es, ls, lpb, bstride, tw64);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_pack(const double2* in, float2* K, int Nx, int Ny, int Kx, double scale, hipStream_t s) {
+  const size_t tot = (size_t)6 * Kx * Ny;
+  hipLaunchKernelGGL(k_pair_pack, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, in, K, Nx, Ny, Kx, scale);
   return hipGetLastError();
 }
 

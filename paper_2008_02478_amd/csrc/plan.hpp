@@ -60,6 +60,45 @@ struct GLTable {
 // (ms_mesh == nullptr: the scalar ms), its spectrum slab at b * Tb points and
 // its energy partials at b * (partials per member).
 
+// One plane pair (target p, source q) of a coupled group on the padded fine
+// in-plane grid: R = (u fx + ox, v fy + oy, oz) for lattice offsets (u, v).
+struct PairGeom {
+  double ht[3], hs[3];
+  double fx, fy, ox, oy, oz;
+  int Nx, Ny, Lx, Ly;
+};
+
+// Coupled layers (Sec. 3, Eq. 4): every z plane of every mesh of a group is
+// embedded in one fine in-plane lattice (the finest pitch of the group).
+// Plane p's cell (i, j) sits at fine (ox + i sx, oy + j sy); its true centre is
+// offset by (dxo, dyo) from that lattice point (coarser cells), which the
+// pair kernels carry.
+constexpr int MAXP = 8;
+struct PlaneInfo {
+  long long moff;      // float offset of the owning mesh in the batch vectors
+  int nx, ny, nz, k;   // owning mesh dims and this plane's z index
+  int sx, sy, ox, oy;  // embedding strides and offsets on the fine lattice
+  int gid;             // global mesh index (Ms, energy, gE)
+  float vol;           // cell volume of the owning mesh (m^3)
+};
+
+struct LayerArgs {
+  const PlaneInfo* pl;         // device table of P planes
+  int P, Ly, nTiles, Kx;
+  const float* m; float* H; float2* T; const float2* tw;
+  const float* ms_mesh; float ms;
+  int backward;                // input times 1/V, output times Ms V (adjoint)
+  int accumulate;
+  const float* aux; const double* beta_ptr; double beta_scale;
+};
+
+struct CoupleArgs {
+  float2* S; const float2* K;  // S[c][p][kx][ky], K[pair][component][kx][ky]
+  const PlaneInfo* pl;
+  int Kx, NY, Nx;
+  double* epart;               // per workgroup and plane, or nullptr
+};
+
 struct FwdArgs {
   const float* m; const float* Ms; float ms;
   float2* T; const float2* tw;
@@ -72,6 +111,7 @@ struct MidArgs {
   double* epart;               // one partial per workgroup, or nullptr
   int ny, Nz, Nx, nTiles, Kx, Kyh, Kzh, kw_halves;
   int nb; size_t Tb; int nblk1; // workgroups per member
+  float2* S;                    // full y spectra [c][plane][kx][ky] (split y passes)
 };
 
 struct InvArgs {

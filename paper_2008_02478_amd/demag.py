@@ -116,21 +116,25 @@ class DemagPlan:
 
 
 class DemagBatch:
-    """Batch of independent meshes: meshes = [((nx, ny, nz), (dx, dy, dz)), ...].
+    """Batch of meshes: meshes = [((nx, ny, nz), (dx, dy, dz)), ...], with
+    optional origins (lower corners, metres) and group ids (meshes sharing an
+    id >= 0 are coupled layers, Sec. 3 Eq. 4; others independent).
     Vectors of all meshes are concatenated (mesh order, each SoA
     [3][nz][ny][nx]) into one flat float32 tensor of `total` elements;
     `view(x, i)` returns mesh i's block.  Meshes of equal geometry share one
     kernel spectrum and run through the same launches."""
 
-    def __init__(self, meshes, device=None):
+    def __init__(self, meshes, device=None, origins=None, groups=None):
         self._lib = _l.load()
         self.meshes = [(tuple(int(v) for v in n), tuple(float(v) for v in h)) for n, h in meshes]
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         k = len(self.meshes)
         dims = (ctypes.c_int * (3 * k))(*[v for n, _ in self.meshes for v in n])
         cells = (ctypes.c_double * (3 * k))(*[v for _, h in self.meshes for v in h])
+        orig = (ctypes.c_double * (3 * k))(*[float(v) for o in origins for v in o]) if origins is not None else None
+        grp = (ctypes.c_int * k)(*[int(v) for v in groups]) if groups is not None else None
         self._p = ctypes.c_void_p()
-        _l.check(self._lib.demag_setup_batch(ctypes.byref(self._p), k, dims, cells, 0, 0))
+        _l.check(self._lib.demag_setup_batch(ctypes.byref(self._p), k, dims, cells, orig, grp, 0, 0))
         nm, tot = ctypes.c_int(), ctypes.c_size_t()
         offs = (ctypes.c_longlong * k)()
         _l.check(self._lib.demag_batch_layout(self._p, ctypes.byref(nm), offs, ctypes.byref(tot)))

@@ -24,7 +24,8 @@ _SIGS = {
     "demag_energy": [_vp, _vp, _vp, _flt, _vp, _vp, _vp],
     "demag_backward": [_vp, _vp, _vp, _flt, _vp, _vp, _vp, _uint, _vp],
     "demag_set_timing_events": [_vp, ctypes.POINTER(_vp), _int],
-    "demag_setup_batch": [ctypes.POINTER(_vp), _int, ctypes.POINTER(_int), ctypes.POINTER(_dbl), _uint, _int],
+    "demag_setup_batch": [ctypes.POINTER(_vp), _int, ctypes.POINTER(_int), ctypes.POINTER(_dbl),
+                          ctypes.POINTER(_dbl), ctypes.POINTER(_int), _uint, _int],
     "demag_batch_layout": [_vp, ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_longlong),
                            ctypes.POINTER(ctypes.c_size_t)],
     "demag_field_batch": [_vp, _vp, _vp, _flt, _vp, _uint, _vp, _vp],

@@ -125,7 +125,7 @@ def test_batch_setup_and_layout(lib):
     dims = (ctypes.c_int * 9)(4, 3, 2, 8, 8, 1, 4, 3, 2)
     cells = (ctypes.c_double * 9)(1e-9, 1e-9, 1e-9, 5e-9, 5e-9, 3e-9, 1e-9, 1e-9, 1e-9)
     p = ctypes.c_void_p()
-    assert lib.demag_setup_batch(ctypes.byref(p), 3, dims, cells, 0, 0) == L.OK
+    assert lib.demag_setup_batch(ctypes.byref(p), 3, dims, cells, None, None, 0, 0) == L.OK
     try:
         nm, tot = ctypes.c_int(), ctypes.c_size_t()
         offs = (ctypes.c_longlong * 3)()
@@ -146,7 +146,7 @@ def test_batch_setup_rejects(lib, n, code):
     dims = (ctypes.c_int * 6)(4, 3, 2, 4, 3, 17)
     cells = (ctypes.c_double * 6)(1e-9, 1e-9, 1e-9, 1e-9, 1e-9, 1e-9)
     p = ctypes.c_void_p()
-    assert lib.demag_setup_batch(ctypes.byref(p), n, dims, cells, 0, 0) == code
+    assert lib.demag_setup_batch(ctypes.byref(p), n, dims, cells, None, None, 0, 0) == code
     assert not p.value
 
 
@@ -159,3 +159,24 @@ def test_single_plan_refuses_batch_calls(lib):
         assert lib.demag_backward_batch(p, dummy, None, 1.0, None, None, dummy, 0, None) == L.EINVAL
     finally:
         lib.demag_destroy(p)
+
+
+def test_coupled_group_validation(lib):
+    dims = (ctypes.c_int * 9)(8, 8, 2, 8, 8, 1, 4, 4, 3)
+    ok_cells = (ctypes.c_double * 9)(1e-9, 1e-9, 1e-9, 1e-9, 1e-9, 1e-9, 2e-9, 2e-9, 2e-9)
+    origins = (ctypes.c_double * 9)(0, 0, 0, 0, 0, 3e-9, 0, 0, 7e-9)
+    groups = (ctypes.c_int * 3)(0, 0, 0)
+    p = ctypes.c_void_p()
+    assert lib.demag_setup_batch(ctypes.byref(p), 3, dims, ok_cells, origins, groups, 0, 0) == L.OK
+    lib.demag_destroy(p)
+    # non power-of-two in-plane ratio
+    bad = (ctypes.c_double * 9)(1e-9, 1e-9, 1e-9, 1e-9, 1e-9, 1e-9, 3e-9, 3e-9, 2e-9)
+    assert lib.demag_setup_batch(ctypes.byref(p), 3, dims, bad, origins, groups, 0, 0) == L.EUNSUPPORTED
+    # origin off the fine lattice
+    off = (ctypes.c_double * 9)(0, 0, 0, 0.3e-9, 0, 3e-9, 0, 0, 7e-9)
+    assert lib.demag_setup_batch(ctypes.byref(p), 3, dims, ok_cells, off, groups, 0, 0) == L.EUNSUPPORTED
+    # too many planes (2 + 1 + 6 > 8)
+    dims9 = (ctypes.c_int * 9)(8, 8, 2, 8, 8, 1, 4, 4, 6)
+    assert lib.demag_setup_batch(ctypes.byref(p), 3, dims9, ok_cells, origins, groups, 0, 0) == L.EUNSUPPORTED
+    # groups without origins
+    assert lib.demag_setup_batch(ctypes.byref(p), 3, dims, ok_cells, None, groups, 0, 0) == L.EINVAL
