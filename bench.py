@@ -48,40 +48,53 @@ def mid_pass_bytes(n):
     return 2 * spec + 6 * Kz * Ky * Kx * 4
 
 
-def bench_batch(torch, reps=20):
-    """64 independent 64x64x1 meshes of 5x5x3 nm cells (Ms uniform in
-    [5e5, 1.4e6] A/m, seed 7; random unit fields, seeds 100+i): 64 plain
-    demag_field calls on one stream (B0) against one batched call replayed
-    from a HIP graph (B1), both with the energy."""
+def bench_batch(torch, reps=10):
+    """Batched multi-mesh workload: three coupled layers (512x512x2 and
+    512x512x1 of 1 nm cells, 256x256x3 of 2 nm cells, 1 nm and 3 nm
+    spacings) plus 64 independent 64x64x1 meshes of 5x5x3 nm cells; Ms uniform
+    in [5e5, 1.4e6] A/m (seed 7), random unit fields (seeds 100+i); energies
+    included.  B0: the plain launches, 64 demag_field calls plus the coupled
+    group's own batch call, on one stream.  B1: one batched call for all 67
+    meshes replayed from a HIP graph."""
     import ctypes
     from paper_2008_02478_amd import inputs, lib
     from paper_2008_02478_amd.demag import DemagBatch, DemagPlan
     L = lib.load()
-    n, h, k = (64, 64, 1), (5e-9, 5e-9, 3e-9), 64
-    Ms = inputs.uniform(k, 5e5, 1.4e6, seed=7).astype(np.float32)
-    plan = DemagPlan(n, h)
-    ms = [torch.from_numpy(inputs.unit_sphere(n, seed=100 + i)).cuda() for i in range(k)]
+    layers = [((512, 512, 2), (1e-9, 1e-9, 1e-9)), ((512, 512, 1), (1e-9, 1e-9, 1e-9)),
+              ((256, 256, 3), (2e-9, 2e-9, 2e-9))]
+    lorig = [(0.0, 0.0, 0.0), (0.0, 0.0, 3e-9), (0.0, 0.0, 7e-9)]
+    small, k = ((64, 64, 1), (5e-9, 5e-9, 3e-9)), 64
+    meshes = layers + [small] * k
+    Ms = inputs.uniform(len(meshes), 5e5, 1.4e6, seed=7).astype(np.float32)
+    full = DemagBatch(meshes, origins=lorig + [(0.0, 0.0, 0.0)] * k, groups=[0, 0, 0] + [-1] * k)
+    grp = DemagBatch(layers, origins=lorig, groups=[0, 0, 0])
+    plan = DemagPlan(*small)
+    mf = torch.empty(full.total, dtype=torch.float32, device="cuda")
+    for i, (n, _) in enumerate(meshes):
+        full.view(mf, i).copy_(torch.from_numpy(inputs.unit_sphere(n, seed=100 + i)).cuda())
+    Hf = torch.empty_like(mf)
+    Ef = torch.empty(len(meshes), dtype=torch.float64, device="cuda")
+    Msf = torch.from_numpy(Ms).cuda()
+    mg = mf[:grp.total].clone()
+    Hg = torch.empty_like(mg)
+    Eg = torch.empty(3, dtype=torch.float64, device="cuda")
+    Msg = Msf[:3].clone()
+    ms = [full.view(mf, 3 + i).contiguous() for i in range(k)]
     Hs = [torch.empty_like(x) for x in ms]
     Es = torch.empty(k, dtype=torch.float64, device="cuda")
-    b = DemagBatch([(n, h)] * k)
-    mb = torch.cat([x.reshape(-1) for x in ms])
-    Hb = torch.empty_like(mb)
-    Eb = torch.empty(k, dtype=torch.float64, device="cuda")
-    Msd = torch.from_numpy(Ms).cuda()
+    st = lambda: ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
 
     def b0():
-        st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        lib.check(L.demag_field_batch(grp._p, P(mg), P(Msg), 0.0, P(Hg), 0, P(Eg), st()))
         for i in range(k):
-            lib.check(L.demag_field(plan._p, ctypes.c_void_p(ms[i].data_ptr()), None, float(Ms[i]),
-                                    ctypes.c_void_p(Hs[i].data_ptr()), 0,
-                                    ctypes.c_void_p(Es.data_ptr() + 8 * i), st))
+            lib.check(L.demag_field(plan._p, P(ms[i]), None, float(Ms[3 + i]), P(Hs[i]), 0,
+                                    ctypes.c_void_p(Es.data_ptr() + 8 * i), st()))
 
     def b1_call():
-        lib.check(L.demag_field_batch(b._p, ctypes.c_void_p(mb.data_ptr()), ctypes.c_void_p(Msd.data_ptr()), 0.0,
-                                      ctypes.c_void_p(Hb.data_ptr()), 0, ctypes.c_void_p(Eb.data_ptr()),
-                                      ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        lib.check(L.demag_field_batch(full._p, P(mf), P(Msf), 0.0, P(Hf), 0, P(Ef), st()))
 
-    for _ in range(3):
+    for _ in range(2):
         b0()
         b1_call()
     torch.cuda.synchronize()
@@ -104,8 +117,10 @@ def bench_batch(torch, reps=20):
         e1.record()
         torch.cuda.synchronize()
         t[name] = e0.elapsed_time(e1) / reps
-    same = all(torch.equal(Hs[i].reshape(-1), b.view(Hb, i).reshape(-1)) for i in range(k)) and torch.equal(Es, Eb)
-    return {"workload": "64 independent 64x64x1 meshes, 5x5x3 nm cells, energy included",
+    same = (torch.equal(Hg, Hf[:grp.total]) and torch.equal(Eg, Ef[:3]) and torch.equal(Es, Ef[3:])
+            and all(torch.equal(Hs[i].reshape(-1), full.view(Hf, 3 + i).reshape(-1)) for i in range(k)))
+    return {"workload": "3 coupled layers (512x512x2 + 512x512x1 of 1 nm, 256x256x3 of 2 nm) + 64 independent "
+                        "64x64x1 meshes, energies included",
             "per_mesh_calls_ms": t["B0"], "batched_graph_ms": t["B1"], "speedup": t["B0"] / t["B1"],
             "identical_results": bool(same)}
 

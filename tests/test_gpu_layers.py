@@ -132,3 +132,41 @@ def test_mixed_batch(torch):
     err = rel_l2(np.concatenate([b.view(H, i).cpu().numpy().ravel() for i in range(3)]),
                  np.concatenate([x.ravel() for x in Hr]))
     assert err < TOL
+
+
+C5_LAYERS = [((512, 512, 2), (1e-9, 1e-9, 1e-9)), ((512, 512, 1), (1e-9, 1e-9, 1e-9)),
+             ((256, 256, 3), (2e-9, 2e-9, 2e-9))]
+C5_ORIG = [(0.0, 0.0, 0.0), (0.0, 0.0, 3e-9), (0.0, 0.0, 7e-9)]
+
+
+def test_full_size_layers_and_small_meshes(torch):
+    # three coupled layers (1 nm and 3 nm spacings) plus 64 independent
+    # 64x64x1 meshes, one plan; sampled direct sums of Eq. 4 for the layers
+    from paper_2008_02478_amd.demag import DemagBatch
+    meshes = C5_LAYERS + [((64, 64, 1), (5e-9, 5e-9, 3e-9))] * 64
+    origins = C5_ORIG + [(0.0, 0.0, 0.0)] * 64
+    groups = [0, 0, 0] + [-1] * 64
+    Ms = inputs.uniform(len(meshes), 5e5, 1.4e6, seed=7).astype(np.float32)
+    say("full-size layers + 64 small meshes")
+    b = DemagBatch(meshes, origins=origins, groups=groups)
+    m = torch.empty(b.total, dtype=torch.float32, device="cuda")
+    host = []
+    for i, (n, _) in enumerate(meshes):
+        x = inputs.unit_sphere(n, seed=100 + i)
+        host.append(x)
+        b.view(m, i).copy_(to_dev(x, torch))
+    H, E = b.field(m, torch.from_numpy(Ms).cuda(), energy=True)
+    torch.cuda.synchronize()
+    Hl = [b.view(H, i).cpu().numpy() for i in range(3)]
+    M = [float(Ms[i]) * host[i].astype(np.float64) for i in range(3)]
+    targets = [(0, (1, 100, 200)), (1, (0, 511, 3)), (2, (2, 128, 17)), (2, (0, 0, 255))]
+    say("  oracle direct sums at 4 cells")
+    Hr = ml.field_at([(n, h, o) for (n, h), o in zip(C5_LAYERS, C5_ORIG)], M, targets)
+    got = np.array([Hl[i][:, k, j, x] for i, (k, j, x) in targets])
+    err = rel_l2(got, Hr)
+    say(f"  sampled rel-L2 {err:.2e}")
+    assert err < TOL
+    for i in (3, 40, 66):
+        n, h = meshes[i]
+        Hs = conv.fft_conv(float(Ms[i]) * host[i].astype(np.float64), h)
+        assert rel_l2(b.view(H, i).cpu().numpy(), Hs) < TOL
