@@ -48,7 +48,7 @@ def mid_pass_bytes(n):
     return 2 * spec + 6 * Kz * Ky * Kx * 4
 
 
-def bench_batch(torch, reps=10):
+def bench_batch(torch, reps=10, tune=True):
     """Batched multi-mesh workload: three coupled layers (512x512x2 and
     512x512x1 of 1 nm cells, 256x256x3 of 2 nm cells, 1 nm and 3 nm
     spacings) plus 64 independent 64x64x1 meshes of 5x5x3 nm cells; Ms uniform
@@ -69,6 +69,9 @@ def bench_batch(torch, reps=10):
     full = DemagBatch(meshes, origins=lorig + [(0.0, 0.0, 0.0)] * k, groups=[0, 0, 0] + [-1] * k)
     grp = DemagBatch(layers, origins=lorig, groups=[0, 0, 0])
     plan = DemagPlan(*small)
+    if tune:
+        for x in (full, grp, plan):
+            x.autotune()
     mf = torch.empty(full.total, dtype=torch.float32, device="cuda")
     for i, (n, _) in enumerate(meshes):
         full.view(mf, i).copy_(torch.from_numpy(inputs.unit_sphere(n, seed=100 + i)).cuda())
@@ -122,7 +125,7 @@ def bench_batch(torch, reps=10):
     return {"workload": "3 coupled layers (512x512x2 + 512x512x1 of 1 nm, 256x256x3 of 2 nm) + 64 independent "
                         "64x64x1 meshes, energies included",
             "per_mesh_calls_ms": t["B0"], "batched_graph_ms": t["B1"], "speedup": t["B0"] / t["B1"],
-            "identical_results": bool(same)}
+            "identical_results": bool(same), "schedules": full.schedules()}
 
 
 def main():
@@ -132,6 +135,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="512x512x16", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch schedules")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
@@ -158,6 +162,10 @@ def main():
     plan = DemagPlan(n, h, device=dev)
     torch.cuda.synchronize()
     setup_s = time.time() - t0
+    t0 = time.time()
+    if not args.no_tune:
+        plan.autotune()
+    tune_s = time.time() - t0
     m = torch.from_numpy(m_np).to(dev)
     G = torch.from_numpy(G_np).to(dev)
     H = torch.empty_like(m)
@@ -244,6 +252,8 @@ def main():
         "evals_per_s_fwd_bwd_pairs": 1e3 / ms_step,
         "pass_us": pass_us,
         "setup_s": setup_s,
+        "tune_s": tune_s,
+        "schedule": plan.schedules()[0],
         "roofline": {
             "bound": "hbm",
             "kernel": "k_mid (y FFT + kernel product + inverse y FFT)",
@@ -256,7 +266,7 @@ def main():
         },
     }
 
-    out["batched_multi_mesh"] = bench_batch(torch)
+    out["batched_multi_mesh"] = bench_batch(torch, tune=not args.no_tune)
 
     if not args.no_cpu_baseline:
         from oracle import conv

@@ -143,6 +143,43 @@ int demag_backward_batch(const demag_plan* plan, const float* d_G, const float* 
  * NULL (or count 0) turns recording off.  Host-only bookkeeping. */
 int demag_set_timing_events(demag_plan* plan, void* const* events, int count);
 
+/* Launch schedules.  Each plan has parts: one per group of identical
+ * independent meshes (a single-mesh plan has one), then one per coupled
+ * group.  A part's schedule is its launch shape:
+ *   yg    y rows per workgroup of the x passes (meshes only; 0 for groups),
+ *   kw    kx lines per workgroup of the middle (y) pass: 2, 4 or 8,
+ *   radix points per lane of its y line FFTs (Ny/2 points per line): the
+ *         default for the length, or 4 / 8 / 16 for Ny/2 of 256 and 512 when
+ *         that leaves at most 64 lanes per line.
+ * All schedules compute the same convolution (Sec. 3, Eq. 4); they differ
+ * only in speed and FP32 rounding order.  Host only. */
+int demag_schedule_count(const demag_plan* plan, int* nparts);
+int demag_get_schedule(const demag_plan* plan, int part, int* yg, int* kw, int* radix);
+
+/* Sets part's schedule; 0 keeps a field.  DEMAG_EINVAL for a yg outside
+ * 1..ny or beyond 160 KiB of LDS, a kw other than 2/4/8, a non-zero yg on a
+ * coupled group; DEMAG_EUNSUPPORTED for a radix not offered for the length.
+ * Affects later calls only (graphs captured earlier keep their launches);
+ * not safe against concurrent calls on the same plan. */
+int demag_set_schedule(demag_plan* plan, int part, int yg, int kw, int radix);
+
+enum { DEMAG_TUNE_FORCE = 1 };    /* measure even where the cache has an entry */
+
+/* Launch-shape tuner.  For each part: if cache_path names a schedule cache
+ * (JSON, "demag-schedule-cache/1") holding an entry for this device and
+ * geometry, apply it; else time every candidate schedule on `stream` with
+ * HIP events (x passes over the yg candidates, then the middle pass over
+ * kw x radix), keep the fastest and, when cache_path is given, write it back
+ * (temporary file + rename).  Measuring needs a bound plan (DEMAG_ESTATE) and,
+ * for mesh parts, d_m and d_H laid out like the plan's vectors: d_m is only
+ * read (its values do not matter), d_H and the plan's work buffer are
+ * overwritten.  It synchronizes the stream: set-up time, not for graph
+ * capture.  *measured (may be NULL) receives the number of parts timed.
+ * DEMAG_EINVAL for an unreadable or malformed cache or an entry holding an
+ * unsupported schedule; DEMAG_EHIP without a device. */
+int demag_autotune(demag_plan* plan, const float* d_m, float* d_H, const char* cache_path, unsigned flags,
+                   int* measured, void* stream);
+
 /* Free a plan (host memory only).  NULL is accepted. */
 int demag_destroy(demag_plan* plan);
 

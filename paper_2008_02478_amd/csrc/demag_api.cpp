@@ -20,6 +20,7 @@
 #include "fft_core.hpp"
 #include "launch.hpp"
 #include "plan.hpp"
+#include "tune_cache.hpp"
 
 using namespace demag;
 
@@ -164,10 +165,7 @@ int make_geom(int nx, int ny, int nz, double dx, double dy, double dz, Geom& g, 
   if (yg < 1) yg = 1;
   g.yg = yg;
   g.mid_kw = 4;
-  if (const char* kw = std::getenv("DEMAG_MID_KW")) {
-    const int v = std::atoi(kw);
-    g.mid_kw = (v == 2 || v == 8) ? v : 4;
-  }
+  g.mid_r = 0;
   return DEMAG_OK;
 }
 
@@ -185,7 +183,7 @@ void layout(demag_plan* p) {
     s.t_off = wb;
     wb += align256(nb * spectrum_elems(g) * sizeof(float2));
     const size_t ncell = (size_t)g.nx * g.ny * g.nz;
-    s.parts = (size_t)mid_blocks(g);
+    s.parts = (size_t)mid_blocks_max(g);   // room for every middle-pass schedule
     const size_t ecb = (size_t)energy_cell_blocks(ncell);
     if (ecb > s.parts) s.parts = ecb;
     s.e_off = wb;
@@ -276,6 +274,7 @@ int make_group(const std::vector<int>& idx, const int* dims, const double* cells
   g.dx = fx; g.dy = fy; g.dz = 1.0;
   g.yg = 1;
   g.mid_kw = 4;
+  g.mid_r = 0;
   if ((size_t)P * xrow_pitch_rt(g.lnx) * sizeof(float2) + 8192 > 160 * 1024)
     return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": coupled planes of one fine row must fit in 160 KiB of LDS");
   G.fx = fx;
@@ -348,6 +347,12 @@ int build_group(const Group& G, hipStream_t s) {
   return rc;
 }
 
+MidArgs group_mid_args(const demag_plan* p, const Group& G) {
+  const Geom& g = G.g;
+  return MidArgs{G.T, nullptr, p->tw, nullptr, g.ny, g.Nz, g.Nx, g.nTiles, g.Kx, g.Kyh, g.Kzh,
+                 TILE / mid_kw(g), 1, spectrum_elems(g), mid_blocks(g), G.S};
+}
+
 int run_groups(const demag_plan* p, const float* d_in, const float* ms_mesh, float Ms, float* d_out, unsigned flags,
                double* d_energy, bool backward, const float* d_H, const double* d_gE, hipStream_t s) {
   for (const Group& G : p->groups) {
@@ -357,8 +362,7 @@ int run_groups(const demag_plan* p, const float* d_in, const float* ms_mesh, flo
                  (flags & DEMAG_ACCUMULATE) ? 1 : 0, d_H, d_gE, -MU0};
     hipError_t e = launch_layer_x(g.lnx, la, false, s);
     if (e != hipSuccess) return fail_hip(e, "layer forward pass");
-    MidArgs ma{G.T, nullptr, p->tw, nullptr, g.ny, g.Nz, g.Nx, g.nTiles, g.Kx, g.Kyh, g.Kzh, 2, 1,
-               spectrum_elems(g), g.nTiles * 2 * g.Nz, G.S};
+    const MidArgs ma = group_mid_args(p, G);
     if ((e = launch_mid_split(g, ma, 1, s)) != hipSuccess) return fail_hip(e, "layer y pass");
     CoupleArgs ca{G.S, G.K, G.pl, g.Kx, g.Ny, g.Nx, (d_energy && !backward) ? G.epart : nullptr};
     if ((e = launch_couple(P, ca, s)) != hipSuccess) return fail_hip(e, "layer coupling");
@@ -445,23 +449,29 @@ int mark(const demag_plan* p, int i, hipStream_t s) {
   return e == hipSuccess ? DEMAG_OK : fail_hip(e, "hipEventRecord");
 }
 
+FwdArgs fwd_args(const demag_plan* p, const Sub& sb, const float* src, const float* Ms, float ms,
+                 const float* ms_mesh) {
+  const Geom& g = sb.g;
+  return FwdArgs{src, Ms, ms, sb.T, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, (int)sb.members.size(),
+                 p->batch ? sb.moff : nullptr, ms_mesh, spectrum_elems(g), p->batch ? sb.gid : nullptr};
+}
+
+MidArgs mid_args(const demag_plan* p, const Sub& sb, bool energy) {
+  const Geom& g = sb.g;
+  return MidArgs{sb.T, sb.K, p->tw, energy ? sb.epart : nullptr, g.ny, g.Nz, g.Nx, g.nTiles, g.Kx, g.Kyh, g.Kzh,
+                 TILE / mid_kw(g), (int)sb.members.size(), spectrum_elems(g), mid_blocks(g)};
+}
+
 // forward and middle passes of one sub-plan
 int run_conv(const demag_plan* p, const Sub& sb, const float* src, const float* Ms, float ms,
              const float* ms_mesh, bool energy, hipStream_t s) {
   const Geom& g = sb.g;
-  const int nb = (int)sb.members.size();
-  const long long* moff = p->batch ? sb.moff : nullptr;
-  const int* gid = p->batch ? sb.gid : nullptr;
-  const size_t Tb = spectrum_elems(g);
   int rc = mark(p, 0, s);
   if (rc != DEMAG_OK) return rc;
-  FwdArgs fa{src, Ms, ms, sb.T, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, nb, moff, ms_mesh, Tb, gid};
-  hipError_t e = launch_fwd(g, fa, s);
+  hipError_t e = launch_fwd(g, fwd_args(p, sb, src, Ms, ms, ms_mesh), s);
   if (e != hipSuccess) return fail_hip(e, "forward pass");
   if ((rc = mark(p, 1, s)) != DEMAG_OK) return rc;
-  MidArgs ma{sb.T, sb.K, p->tw, energy ? sb.epart : nullptr, g.ny, g.Nz, g.Nx, g.nTiles, g.Kx, g.Kyh, g.Kzh,
-             TILE / mid_kw(g), nb, Tb, mid_blocks(g)};
-  e = launch_mid(g, ma, s);
+  e = launch_mid(g, mid_args(p, sb, energy), s);
   if (e != hipSuccess) return fail_hip(e, "middle pass");
   return mark(p, 2, s);
 }
@@ -504,6 +514,209 @@ int run_backward(const demag_plan* p, const float* d_G, const float* d_Ms, float
     if ((rc = mark(p, 3, s)) != DEMAG_OK) return rc;
   }
   return DEMAG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launch-shape schedules and their tuner
+// ---------------------------------------------------------------------------
+// A plan has one schedule per part: parts 0 .. subs-1 are the same-geometry
+// sub-plans, the following ones the coupled groups.  The tunables are the y
+// rows per workgroup of the x passes (sub-plans only), the kx lines per
+// workgroup of the middle pass and the radix of its y lines.  Every schedule
+// computes the same convolution; they differ in rounding order and speed.
+
+int part_count(const demag_plan* p) { return (int)(p->subs.size() + p->groups.size()); }
+
+Geom& part_geom(demag_plan* p, int i) {
+  return i < (int)p->subs.size() ? p->subs[i].g : p->groups[i - p->subs.size()].g;
+}
+
+bool yg_ok(const Geom& g, int yg) {
+  if (yg < 1 || yg > g.ny) return false;
+  return (size_t)yg * g.nz * xrow_pitch_rt(g.lnx) * sizeof(float2) + 8192 <= 160 * 1024;
+}
+
+bool kw_ok(int kw) { return kw == 2 || kw == 4 || kw == 8; }
+
+int line_m(const Geom& g) { return g.Ny > 1 ? g.Ny / 2 : 1; }
+
+bool sched_ok(const Geom& g, int kw, int r) { return mid_schedule_ok(line_m(g), kw, r); }
+
+std::vector<int> radix_candidates(const Geom& g) {
+  const int M = line_m(g);
+  std::vector<int> r{line_radix(M)};
+  for (int c : {4, 8, 16})
+    if (c != r[0] && mid_radix_ok(M, c)) r.push_back(c);
+  return r;
+}
+
+InvArgs inv_plain_args(const demag_plan* p, const Sub& sb, float* d_H, unsigned flags, const float* ms_mesh) {
+  const Geom& g = sb.g;
+  return InvArgs{sb.T, d_H, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, (flags & DEMAG_ACCUMULATE) ? 1 : 0,
+                 nullptr, nullptr, 0.0, nullptr, 0.f, 0,
+                 (int)sb.members.size(), p->batch ? sb.moff : nullptr, ms_mesh, spectrum_elems(g),
+                 p->batch ? sb.gid : nullptr};
+}
+
+// Microseconds per call of fn (a launch sequence on s): two warm-up calls,
+// then the best of three timed runs of `reps` calls (reps sized for ~2 ms).
+template <class F>
+int time_calls(hipStream_t s, F&& fn, double& us) {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e;
+  if ((e = hipEventCreate(&a)) != hipSuccess) return fail_hip(e, "hipEventCreate");
+  if ((e = hipEventCreate(&b)) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail_hip(e, "hipEventCreate");
+  }
+  auto run = [&](int n) -> int {
+    for (int i = 0; i < n; ++i) {
+      const int rc = fn();
+      if (rc != DEMAG_OK) return rc;
+    }
+    return DEMAG_OK;
+  };
+  auto timed = [&](int n, double& t) -> int {
+    hipError_t he;
+    if ((he = hipEventRecord(a, s)) != hipSuccess) return fail_hip(he, "hipEventRecord");
+    const int rc = run(n);
+    if (rc != DEMAG_OK) return rc;
+    if ((he = hipEventRecord(b, s)) != hipSuccess) return fail_hip(he, "hipEventRecord");
+    if ((he = hipEventSynchronize(b)) != hipSuccess) return fail_hip(he, "hipEventSynchronize");
+    float ms = 0.f;
+    if ((he = hipEventElapsedTime(&ms, a, b)) != hipSuccess) return fail_hip(he, "hipEventElapsedTime");
+    t = 1000.0 * ms / n;
+    return DEMAG_OK;
+  };
+  int rc = run(2);
+  double t1 = 0.0;
+  if (rc == DEMAG_OK) rc = timed(1, t1);
+  if (rc == DEMAG_OK) {
+    int reps = (int)(2000.0 / (t1 > 1.0 ? t1 : 1.0));
+    reps = reps < 3 ? 3 : (reps > 50 ? 50 : reps);
+    us = 1e300;
+    for (int trial = 0; trial < 3 && rc == DEMAG_OK; ++trial) {
+      double t = 0.0;
+      rc = timed(reps, t);
+      if (rc == DEMAG_OK && t < us) us = t;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return rc;
+}
+
+// Measure the candidates of sub-plan sb and keep the fastest in its geometry.
+int tune_sub(demag_plan* p, Sub& sb, const float* d_m, float* d_H, hipStream_t s, TuneEntry& out) {
+  Geom& g = sb.g;
+  const int d = g.yg;
+  std::vector<int> ygs;
+  for (int c : {d / 2, d, 2 * d, 4 * d})
+    if (yg_ok(g, c) && std::find(ygs.begin(), ygs.end(), c) == ygs.end()) ygs.push_back(c);
+  double best = 1e300;
+  int best_yg = d;
+  for (int yg : ygs) {
+    g.yg = yg;
+    double us = 0.0;
+    const int rc = time_calls(s, [&]() -> int {
+      hipError_t e = launch_fwd(g, fwd_args(p, sb, d_m, nullptr, 1.0f, nullptr), s);
+      if (e == hipSuccess) e = launch_inv(g, inv_plain_args(p, sb, d_H, 0u, nullptr), s);
+      return e == hipSuccess ? DEMAG_OK : fail_hip(e, "x passes");
+    }, us);
+    if (rc != DEMAG_OK) {
+      g.yg = d;
+      return rc;
+    }
+    if (us < best) {
+      best = us;
+      best_yg = yg;
+    }
+  }
+  g.yg = best_yg;
+  out.yg = best_yg;
+  out.x_us = best;
+  const int kw0 = g.mid_kw, r0 = g.mid_r;
+  best = 1e300;
+  int best_kw = mid_kw(g), best_r = mid_radix(g);
+  for (int kw : {2, 4, 8}) {
+    for (int r : radix_candidates(g)) {
+      if (!sched_ok(g, kw, r)) continue;
+      g.mid_kw = kw;
+      g.mid_r = r;
+      double us = 0.0;
+      const int rc = time_calls(s, [&]() -> int {
+        const hipError_t e = launch_mid(g, mid_args(p, sb, false), s);
+        return e == hipSuccess ? DEMAG_OK : fail_hip(e, "middle pass");
+      }, us);
+      if (rc != DEMAG_OK) {
+        g.mid_kw = kw0;
+        g.mid_r = r0;
+        return rc;
+      }
+      if (us < best) {
+        best = us;
+        best_kw = kw;
+        best_r = r;
+      }
+    }
+  }
+  g.mid_kw = best_kw;
+  g.mid_r = best_r;
+  out.kw = best_kw;
+  out.radix = best_r;
+  out.mid_us = best;
+  return DEMAG_OK;
+}
+
+// Coupled group: the two split y passes are the tunable ones.
+int tune_group(demag_plan* p, Group& G, hipStream_t s, TuneEntry& out) {
+  Geom& g = G.g;
+  const int kw0 = g.mid_kw, r0 = g.mid_r;
+  double best = 1e300;
+  int best_kw = mid_kw(g), best_r = mid_radix(g);
+  for (int kw : {2, 4, 8}) {
+    for (int r : radix_candidates(g)) {
+      if (!sched_ok(g, kw, r)) continue;
+      g.mid_kw = kw;
+      g.mid_r = r;
+      double us = 0.0;
+      const int rc = time_calls(s, [&]() -> int {
+        const MidArgs ma = group_mid_args(p, G);
+        hipError_t e = launch_mid_split(g, ma, 1, s);
+        if (e == hipSuccess) e = launch_mid_split(g, ma, 2, s);
+        return e == hipSuccess ? DEMAG_OK : fail_hip(e, "layer y passes");
+      }, us);
+      if (rc != DEMAG_OK) {
+        g.mid_kw = kw0;
+        g.mid_r = r0;
+        return rc;
+      }
+      if (us < best) {
+        best = us;
+        best_kw = kw;
+        best_r = r;
+      }
+    }
+  }
+  g.mid_kw = best_kw;
+  g.mid_r = best_r;
+  out.yg = 0;
+  out.kw = best_kw;
+  out.radix = best_r;
+  out.mid_us = best;
+  return DEMAG_OK;
+}
+
+std::string part_key(const demag_plan* p, int i, const std::string& dev) {
+  char buf[160];
+  if (i < (int)p->subs.size()) {
+    const Sub& sb = p->subs[i];
+    std::snprintf(buf, sizeof buf, "|mesh %dx%dx%d nb=%d", sb.g.nx, sb.g.ny, sb.g.nz, (int)sb.members.size());
+  } else {
+    const Group& G = p->groups[i - p->subs.size()];
+    std::snprintf(buf, sizeof buf, "|layers %dx%d planes=%d", G.g.nx, G.g.ny, (int)G.planes.size());
+  }
+  return dev + buf;
 }
 
 }  // namespace
@@ -764,6 +977,85 @@ int demag_set_timing_events(demag_plan* p, void* const* events, int count) {
     p->ev[i] = static_cast<hipEvent_t>(events[i]);
   }
   p->timing = true;
+  return DEMAG_OK;
+}
+
+int demag_schedule_count(const demag_plan* p, int* nparts) {
+  if (!p || !nparts) return fail(DEMAG_EINVAL, "demag_schedule_count: NULL argument");
+  *nparts = part_count(p);
+  return DEMAG_OK;
+}
+
+int demag_get_schedule(const demag_plan* p, int part, int* yg, int* kw, int* radix) {
+  if (!p || !yg || !kw || !radix) return fail(DEMAG_EINVAL, "demag_get_schedule: NULL argument");
+  if (part < 0 || part >= part_count(p)) return fail(DEMAG_EINVAL, "demag_get_schedule: part out of range");
+  const Geom& g = part_geom(const_cast<demag_plan*>(p), part);
+  *yg = part < (int)p->subs.size() ? g.yg : 0;
+  *kw = mid_kw(g);
+  *radix = mid_radix(g);
+  return DEMAG_OK;
+}
+
+int demag_set_schedule(demag_plan* p, int part, int yg, int kw, int radix) {
+  if (!p) return fail(DEMAG_EINVAL, "demag_set_schedule: plan is NULL");
+  if (part < 0 || part >= part_count(p)) return fail(DEMAG_EINVAL, "demag_set_schedule: part out of range");
+  Geom& g = part_geom(p, part);
+  const bool sub = part < (int)p->subs.size();
+  if (yg != 0 && (!sub || !yg_ok(g, yg)))
+    return fail(DEMAG_EINVAL, sub ? "demag_set_schedule: yg must be in 1..ny and fit the x pass in 160 KiB of LDS"
+                                  : "demag_set_schedule: coupled groups take yg = 0");
+  if (kw != 0 && !kw_ok(kw)) return fail(DEMAG_EINVAL, "demag_set_schedule: kw must be 2, 4 or 8");
+  if (radix != 0 && !mid_radix_ok(line_m(g), radix))
+    return fail(DEMAG_EUNSUPPORTED, "demag_set_schedule: radix not available for this y length");
+  if (!sched_ok(g, kw ? kw : mid_kw(g), radix ? radix : mid_radix(g)))
+    return fail(DEMAG_EUNSUPPORTED, "demag_set_schedule: this kw and radix need more than 128 registers per lane");
+  if (yg) g.yg = yg;
+  if (kw) g.mid_kw = kw;
+  if (radix) g.mid_r = radix;
+  return DEMAG_OK;
+}
+
+int demag_autotune(demag_plan* p, const float* d_m, float* d_H, const char* cache_path, unsigned flags,
+                   int* measured, void* stream) {
+  if (!p) return fail(DEMAG_EINVAL, "demag_autotune: plan is NULL");
+  if (flags & ~(unsigned)DEMAG_TUNE_FORCE) return fail(DEMAG_EINVAL, "demag_autotune: unknown flags");
+  if (measured) *measured = 0;
+  TuneMap cache;
+  std::string err;
+  if (cache_path && !tune_cache_read(cache_path, cache, err)) return fail(DEMAG_EINVAL, "demag_autotune: " + err);
+  int dev = p->device;
+  hipError_t e;
+  if (dev < 0 && (e = hipGetDevice(&dev)) != hipSuccess) return fail_hip(e, "hipGetDevice");
+  hipDeviceProp_t prop;
+  if ((e = hipGetDeviceProperties(&prop, dev)) != hipSuccess) return fail_hip(e, "hipGetDeviceProperties");
+  const std::string devkey = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + "CU";
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int nmeas = 0;
+  for (int i = 0; i < part_count(p); ++i) {
+    const std::string key = part_key(p, i, devkey);
+    const bool sub = i < (int)p->subs.size();
+    auto it = cache.find(key);
+    if (it != cache.end() && !(flags & DEMAG_TUNE_FORCE)) {
+      const TuneEntry& c = it->second;
+      Geom& g = part_geom(p, i);
+      if ((sub ? !yg_ok(g, c.yg) : c.yg != 0) || !sched_ok(g, c.kw, c.radix))
+        return fail(DEMAG_EINVAL, "demag_autotune: cache entry '" + key + "' holds an unsupported schedule");
+      if (sub) g.yg = c.yg;
+      g.mid_kw = c.kw;
+      g.mid_r = c.radix;
+      continue;
+    }
+    if (!p->bound) return fail(DEMAG_ESTATE, "demag_autotune: measuring needs a bound plan");
+    if (sub && (!d_m || !d_H)) return fail(DEMAG_EINVAL, "demag_autotune: measuring needs m and H buffers");
+    TuneEntry t;
+    const int rc = sub ? tune_sub(p, p->subs[i], d_m, d_H, s, t) : tune_group(p, p->groups[i - p->subs.size()], s, t);
+    if (rc != DEMAG_OK) return rc;
+    cache[key] = t;
+    ++nmeas;
+  }
+  if (measured) *measured = nmeas;
+  if (cache_path && nmeas > 0 && !tune_cache_write(cache_path, cache, err))
+    return fail(DEMAG_EINVAL, "demag_autotune: " + err);
   return DEMAG_OK;
 }
 

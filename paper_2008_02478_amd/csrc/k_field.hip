@@ -35,7 +35,7 @@ __device__ __forceinline__ void zodd_twiddle(float2 (&v)[NZ / 2]) {
 // forward: x real-to-complex + z
 // ---------------------------------------------------------------------------
 template <int LNX, int LNZ>
-__global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8))) k_fwd_xz(FwdArgs a) {
+__global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_eu(LNX >= 12 ? 2 : 4, 8))) k_fwd_xz(FwdArgs a) {
   constexpr int NX = 1 << LNX;
   constexpr int NZ = 1 << LNZ;
   extern __shared__ float2 smem_base[];
@@ -132,13 +132,8 @@ __device__ __forceinline__ int kz_of(int i, int Nz) {
 
 // threads of the middle pass: two residue jobs per kx (one for a unit y
 // length), each a group of LineShape<M>::T lanes, at least one wavefront
-constexpr int mid_threads(int lny, int kw) {
-  const int ny = 1 << lny;
-  const int m = ny > 1 ? ny / 2 : 1;
-  const int r = m >= 1024 ? 16 : (m >= 8 ? 8 : m);
-  const int nt = (ny > 1 ? 2 : 1) * kw * (m / r);
-  return nt < 64 ? 64 : nt;
-}
+constexpr int mid_radix_of(int lny) { return line_radix(lny > 0 ? (1 << lny) / 2 : 1); }
+constexpr int mid_threads(int lny, int kw, int r) { return mid_threads_rt(lny > 0 ? (1 << lny) / 2 : 1, kw, r); }
 
 template <typename Tv>
 __device__ __forceinline__ Tv block_sum(Tv v, Tv* red) {
@@ -157,20 +152,21 @@ __device__ __forceinline__ Tv block_sum(Tv v, Tv* red) {
 // MODE 1: y FFT only; spectra to S[c][kz][kx][ky] with ky ordered by residue
 //         (r * NY/2 + k' for ky = 2k' + r).
 // MODE 2: inverse y FFT only, from S.
-template <int LNY, int KW, bool ENERGY, int MODE = 0>
-__global__ void __launch_bounds__(mid_threads(LNY, KW)) __attribute__((amdgpu_waves_per_eu(LNY >= 11 ? 2 : 4, 8)))
+// R: points per lane of the M-point y lines (M / R lanes per line).
+template <int LNY, int KW, bool ENERGY, int MODE = 0, int R = mid_radix_of(LNY)>
+__global__ void __launch_bounds__(mid_threads(LNY, KW, R)) __attribute__((amdgpu_waves_per_eu(R >= 16 ? 2 : 4, 8)))
 k_mid(MidArgs a) {
   constexpr int NY = 1 << LNY;
   constexpr int M = NY > 1 ? NY / 2 : 1;
   constexpr int NRES = NY > 1 ? 2 : 1;
-  constexpr int R = LineShape<M>::R;
-  constexpr int T = LineShape<M>::T;
+  static_assert(mid_radix_ok(M, R), "unsupported radix for this line length");
+  constexpr int T = M / R;
   constexpr int JOBS = NRES * KW;
   constexpr int NT = JOBS * T;
   __shared__ double red[16];
   extern __shared__ float2 smem_base[];
   float2* const tab = smem_base;
-  float2* const smem = smem_base + tab_points<M>();
+  float2* const smem = smem_base + tab_points<M, R>();
 
   const int lg0 = xcd_logical(blockIdx.x, gridDim.x);
   const int bm = lg0 / a.nblk1;             // batch member
@@ -334,7 +330,7 @@ k_mid(MidArgs a) {
 // inverse: z + x complex-to-real
 // ---------------------------------------------------------------------------
 template <int LNX, int LNZ>
-__global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8))) k_inv_zx(InvArgs a) {
+__global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_eu(LNX >= 12 ? 2 : 4, 8))) k_inv_zx(InvArgs a) {
   constexpr int NX = 1 << LNX;
   constexpr int NZ = 1 << LNZ;
   extern __shared__ float2 smem_base[];
@@ -536,91 +532,90 @@ int mid_kw(const Geom& g) {
   return 4;
 }
 
-int mid_blocks(const Geom& g) { return g.nTiles * (TILE / mid_kw(g)) * g.Nz; }
+int mid_radix(const Geom& g) {
+  const int M = g.Ny > 1 ? g.Ny / 2 : 1;
+  return (g.mid_r > 0 && mid_radix_ok(M, g.mid_r)) ? g.mid_r : line_radix(M);
+}
 
-template <int LNY, int KW, bool ENERGY>
+int mid_blocks(const Geom& g) { return g.nTiles * (TILE / mid_kw(g)) * g.Nz; }
+int mid_blocks_max(const Geom& g) { return g.nTiles * (TILE / 2) * g.Nz; }
+
+template <int LNY, int KW, bool ENERGY, int MODE, int R>
 static hipError_t mid_launch(const Geom& g, const MidArgs& a, hipStream_t s) {
   constexpr int NY = 1 << LNY;
   constexpr int M = NY > 1 ? NY / 2 : 1;
   constexpr int NRES = NY > 1 ? 2 : 1;
-  size_t lds = (size_t)NRES * KW * lds_points<M, LineShape<M>::R>() * sizeof(float2);
+  size_t lds = (size_t)NRES * KW * lds_points<M, R>() * sizeof(float2);
   const size_t st = (size_t)g.ny * KW * sizeof(float2);
   if (st > lds) lds = st;
-  lds += tab_points<M>() * sizeof(float2);
-  hipError_t e = prep_lds(k_mid<LNY, KW, ENERGY>, lds);
+  lds += tab_points<M, R>() * sizeof(float2);
+  hipError_t e = prep_lds(k_mid<LNY, KW, ENERGY, MODE, R>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_mid<LNY, KW, ENERGY>), dim3(mid_blocks(g) * a.nb), dim3(mid_threads(LNY, KW)), lds, s, a);
+  const int blocks = g.nTiles * (TILE / KW) * g.Nz;
+  hipLaunchKernelGGL((k_mid<LNY, KW, ENERGY, MODE, R>), dim3(blocks * a.nb), dim3(mid_threads(LNY, KW, R)), lds, s,
+                     a);
   return hipGetLastError();
+}
+
+// mode 0: the pipelined pass (energy partials when a.epart is set);
+// 1 / 2: the split y passes of coupled layers
+template <int LNY, int KW, int R>
+static hipError_t mid_mode(const Geom& g, const MidArgs& a, int mode, hipStream_t s) {
+  if constexpr (!mid_schedule_ok(LNY > 0 ? (1 << LNY) / 2 : 1, KW, R)) {
+    return hipErrorInvalidConfiguration;   // not offered (rejected by the plan before launch)
+  } else {
+  if (mode == 1) return mid_launch<LNY, KW, false, 1, R>(g, a, s);
+  if (mode == 2) return mid_launch<LNY, KW, false, 2, R>(g, a, s);
+  return a.epart ? mid_launch<LNY, KW, true, 0, R>(g, a, s) : mid_launch<LNY, KW, false, 0, R>(g, a, s);
+  }
 }
 
 template <int LNY, int KW>
-static hipError_t mid_one(const Geom& g, const MidArgs& a, hipStream_t s) {
-  return a.epart ? mid_launch<LNY, KW, true>(g, a, s) : mid_launch<LNY, KW, false>(g, a, s);
+static hipError_t mid_radix_switch(const Geom& g, const MidArgs& a, int mode, hipStream_t s) {
+  constexpr int M = LNY > 0 ? (1 << LNY) / 2 : 1;
+  constexpr int R0 = line_radix(M);
+  const int r = mid_radix(g);
+  if constexpr (mid_radix_ok(M, 4) && R0 != 4)
+    if (r == 4) return mid_mode<LNY, KW, 4>(g, a, mode, s);
+  if constexpr (mid_radix_ok(M, 8) && R0 != 8)
+    if (r == 8) return mid_mode<LNY, KW, 8>(g, a, mode, s);
+  if constexpr (mid_radix_ok(M, 16) && R0 != 16)
+    if (r == 16) return mid_mode<LNY, KW, 16>(g, a, mode, s);
+  return mid_mode<LNY, KW, R0>(g, a, mode, s);
 }
 
 template <int LNY>
-static hipError_t mid_kw_switch(const Geom& g, const MidArgs& a, hipStream_t s) {
+static hipError_t mid_kw_switch(const Geom& g, const MidArgs& a, int mode, hipStream_t s) {
   switch (mid_kw(g)) {
-    case 2: return mid_one<LNY, 2>(g, a, s);
-    case 8: return mid_one<LNY, 8>(g, a, s);
-    default: return mid_one<LNY, 4>(g, a, s);
+    case 2: return mid_radix_switch<LNY, 2>(g, a, mode, s);
+    case 8: return mid_radix_switch<LNY, 8>(g, a, mode, s);
+    default: return mid_radix_switch<LNY, 4>(g, a, mode, s);
   }
 }
 
-hipError_t launch_mid(const Geom& g, const MidArgs& a, hipStream_t s) {
+static hipError_t mid_dispatch(const Geom& g, const MidArgs& a, int mode, hipStream_t s) {
   switch (g.lny) {
-    case 0: return mid_kw_switch<0>(g, a, s);
-    case 2: return mid_kw_switch<2>(g, a, s);
-    case 3: return mid_kw_switch<3>(g, a, s);
-    case 4: return mid_kw_switch<4>(g, a, s);
-    case 5: return mid_kw_switch<5>(g, a, s);
-    case 6: return mid_kw_switch<6>(g, a, s);
-    case 7: return mid_kw_switch<7>(g, a, s);
-    case 8: return mid_kw_switch<8>(g, a, s);
-    case 9: return mid_kw_switch<9>(g, a, s);
-    case 10: return mid_kw_switch<10>(g, a, s);
-    case 11: return mid_kw_switch<11>(g, a, s);
+    case 0: return mid_kw_switch<0>(g, a, mode, s);
+    case 2: return mid_kw_switch<2>(g, a, mode, s);
+    case 3: return mid_kw_switch<3>(g, a, mode, s);
+    case 4: return mid_kw_switch<4>(g, a, mode, s);
+    case 5: return mid_kw_switch<5>(g, a, mode, s);
+    case 6: return mid_kw_switch<6>(g, a, mode, s);
+    case 7: return mid_kw_switch<7>(g, a, mode, s);
+    case 8: return mid_kw_switch<8>(g, a, mode, s);
+    case 9: return mid_kw_switch<9>(g, a, mode, s);
+    case 10: return mid_kw_switch<10>(g, a, mode, s);
+    case 11: return mid_kw_switch<11>(g, a, mode, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int LNY, int MODE>
-static hipError_t mid_split_one(const Geom& g, const MidArgs& a, hipStream_t s) {
-  constexpr int NY = 1 << LNY;
-  constexpr int M = NY > 1 ? NY / 2 : 1;
-  constexpr int NRES = NY > 1 ? 2 : 1;
-  size_t lds = (size_t)NRES * 4 * lds_points<M, LineShape<M>::R>() * sizeof(float2);
-  const size_t st = (size_t)g.ny * 4 * sizeof(float2);
-  if (st > lds) lds = st;
-  lds += tab_points<M>() * sizeof(float2);
-  hipError_t e = prep_lds(k_mid<LNY, 4, false, MODE>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_mid<LNY, 4, false, MODE>), dim3(g.nTiles * 2 * g.Nz * a.nb), dim3(mid_threads(LNY, 4)), lds, s, a);
-  return hipGetLastError();
-}
-
-template <int LNY>
-static hipError_t mid_split_mode(const Geom& g, const MidArgs& a, int mode, hipStream_t s) {
-  return mode == 1 ? mid_split_one<LNY, 1>(g, a, s) : mid_split_one<LNY, 2>(g, a, s);
-}
+hipError_t launch_mid(const Geom& g, const MidArgs& a, hipStream_t s) { return mid_dispatch(g, a, 0, s); }
 
 // y passes without the kernel product (coupled layers): mode 1 forward into
-// S, mode 2 inverse from S; 4 kx per workgroup
+// S, mode 2 inverse from S
 hipError_t launch_mid_split(const Geom& g, const MidArgs& a, int mode, hipStream_t s) {
-  switch (g.lny) {
-    case 0: return mid_split_mode<0>(g, a, mode, s);
-    case 2: return mid_split_mode<2>(g, a, mode, s);
-    case 3: return mid_split_mode<3>(g, a, mode, s);
-    case 4: return mid_split_mode<4>(g, a, mode, s);
-    case 5: return mid_split_mode<5>(g, a, mode, s);
-    case 6: return mid_split_mode<6>(g, a, mode, s);
-    case 7: return mid_split_mode<7>(g, a, mode, s);
-    case 8: return mid_split_mode<8>(g, a, mode, s);
-    case 9: return mid_split_mode<9>(g, a, mode, s);
-    case 10: return mid_split_mode<10>(g, a, mode, s);
-    case 11: return mid_split_mode<11>(g, a, mode, s);
-    default: return hipErrorInvalidValue;
-  }
+  return mid_dispatch(g, a, mode, s);
 }
 
 hipError_t launch_energy_final(const double* part, int n, double scale, double* out, hipStream_t s, int nb,

@@ -21,7 +21,7 @@
 namespace demag {
 
 template <int LNX>
-__global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8))) k_lfwd(LayerArgs a) {
+__global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_eu(LNX >= 12 ? 2 : 4, 8))) k_lfwd(LayerArgs a) {
   extern __shared__ float2 smem_base[];
   constexpr int PITCH = xrow_pitch<LNX>();
   float2* const tab = smem_base;
@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_e
 }
 
 template <int LNX>
-__global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8))) k_linv(LayerArgs a) {
+__global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_eu(LNX >= 12 ? 2 : 4, 8))) k_linv(LayerArgs a) {
   extern __shared__ float2 smem_base[];
   constexpr int PITCH = xrow_pitch<LNX>();
   float2* const tab = smem_base;

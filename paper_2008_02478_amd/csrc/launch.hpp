@@ -20,6 +20,8 @@ hipError_t launch_layer_energy(const double* part, int nblk, int P, const PlaneI
 int couple_blocks(int Kx, int NY);
 int mid_kw(const Geom& g);
 int mid_blocks(const Geom& g);
+int mid_blocks_max(const Geom& g);
+int mid_radix(const Geom& g);
 int energy_cell_blocks(size_t ncell);
 
 hipError_t launch_tensor(double* out, const Geom& g, const GLTable& gl, hipStream_t s);

@@ -17,6 +17,29 @@ constexpr int line_radix(int M) { return M >= 1024 ? 16 : (M >= 8 ? 8 : M); }
 constexpr int line_pad_shift(int R) { return R >= 16 ? 5 : 3; }
 constexpr int line_lds_points(int M) { return M + (M >> line_pad_shift(line_radix(M))); }
 
+// Radices the middle pass may use for its M-point y lines (M = Ny/2): the
+// default, plus the alternatives the schedule tuner may pick from for the
+// long lines (4 to 64 lanes per line, at most 16 points per lane).
+constexpr bool mid_radix_ok(int M, int R) {
+  if (R == line_radix(M)) return true;
+  if (M != 256 && M != 512) return false;
+  return (R == 4 || R == 8 || R == 16) && M / R <= 64;
+}
+
+// Threads of a middle-pass workgroup: two residue jobs per kx line (one for
+// unit lengths) of M/R lanes each, KW lines, at least one wavefront.
+constexpr int mid_threads_rt(int M, int kw, int R) {
+  const int nt = (M > 1 ? 2 : 1) * kw * (M / R);
+  return nt < 64 ? 64 : nt;
+}
+
+// Schedules offered for the middle pass: a supported radix, and 1024-thread
+// workgroups only for radix <= 4 (at 16 wavefronts per workgroup a lane has
+// 128 registers, too few for 3 components of 8 or 16 points plus twiddles).
+constexpr bool mid_schedule_ok(int M, int kw, int R) {
+  return (kw == 2 || kw == 4 || kw == 8) && mid_radix_ok(M, R) && (mid_threads_rt(M, kw, R) <= 512 || R <= 4);
+}
+
 // LDS points per row of the x passes for Nx = 2^lnx: the half spectrum
 // (Nx/2 + 1 points) and, while the row is transformed, the padded scratch of
 // its two Nx/4-point residue FFTs.
@@ -36,7 +59,8 @@ struct Geom {
   int Kyh, Kzh;        // Ny/2 + 1, Nz/2 + 1 (1 for unit lengths): stored octant
   int nTiles;          // ceil(Kx / TILE)
   int yg;              // y rows per workgroup in the x passes
-  int mid_kw;          // kx lines per workgroup of the middle pass (4 or 8)
+  int mid_kw;          // kx lines per workgroup of the middle pass (2, 4 or 8)
+  int mid_r;           // points per lane of its y line FFT (0: line_radix)
   double dx, dy, dz;
 };
 

@@ -15,9 +15,8 @@ namespace demag {
 
 // LDS points reserved for the stage twiddle table of an M-point line FFT
 // (rounded up to 32 points so that the data after it stays 256-byte aligned).
-template <int M>
+template <int M, int R = LineShape<M>::R>
 constexpr int tab_points() {
-  constexpr int R = LineShape<M>::R;
   return (M > R) ? ((stage_table_size<M, R>() + 31) / 32) * 32 : 0;
 }
 template <int LNX>

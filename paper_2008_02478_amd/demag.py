@@ -22,7 +22,38 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-class DemagPlan:
+class _Schedules:
+    """Launch schedules of a plan's parts (see demag_set_schedule)."""
+
+    def schedules(self):
+        """[{"yg", "kw", "radix"}, ...], one dict per part."""
+        n = ctypes.c_int()
+        _l.check(self._lib.demag_schedule_count(self._p, ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            yg, kw, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            _l.check(self._lib.demag_get_schedule(self._p, i, ctypes.byref(yg), ctypes.byref(kw), ctypes.byref(r)))
+            out.append({"yg": yg.value, "kw": kw.value, "radix": r.value})
+        return out
+
+    def set_schedule(self, part, yg=0, kw=0, radix=0):
+        _l.check(self._lib.demag_set_schedule(self._p, int(part), int(yg), int(kw), int(radix)))
+
+    def autotune(self, cache=None, force=False):
+        """Pick each part's launch schedule by timing the candidates on the
+        current stream (or from the JSON cache file `cache`, which is updated
+        with what was measured).  Returns the number of parts measured."""
+        with torch.cuda.device(self.device):
+            m = torch.zeros(self._vec_shape, dtype=torch.float32, device=self.device)
+            H = torch.empty_like(m)
+            n = ctypes.c_int()
+            path = None if cache is None else str(cache).encode()
+            _l.check(self._lib.demag_autotune(self._p, _ptr(m), _ptr(H), path, _l.TUNE_FORCE if force else 0,
+                                              ctypes.byref(n), _stream()))
+        return n.value
+
+
+class DemagPlan(_Schedules):
     """Plan for one mesh of n = (nx, ny, nz) cells of size cell = (dx, dy, dz)
     metres with open boundaries.  Builds the kernel spectrum on construction."""
 
@@ -54,6 +85,10 @@ class DemagPlan:
     def shape(self):
         nx, ny, nz = self.n
         return (3, nz, ny, nx)
+
+    @property
+    def _vec_shape(self):
+        return self.shape
 
     @property
     def volume(self):
@@ -115,7 +150,7 @@ class DemagPlan:
             self._p = None
 
 
-class DemagBatch:
+class DemagBatch(_Schedules):
     """Batch of meshes: meshes = [((nx, ny, nz), (dx, dy, dz)), ...], with
     optional origins (lower corners, metres) and group ids (meshes sharing an
     id >= 0 are coupled layers, Sec. 3 Eq. 4; others independent).
@@ -147,6 +182,10 @@ class DemagBatch:
             self._wbuf = torch.empty(wb.value + 256, dtype=torch.uint8, device=self.device)
             _l.check(self._lib.demag_bind(self._p, DemagPlan._aligned(self._kbuf), DemagPlan._aligned(self._wbuf),
                                           _stream()))
+
+    @property
+    def _vec_shape(self):
+        return (self.total,)
 
     def view(self, x, i):
         (nx, ny, nz), _ = self.meshes[i]

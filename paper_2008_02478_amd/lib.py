@@ -9,6 +9,7 @@ LIB_PATH = os.environ.get("DEMAG_LIB") or os.path.join(os.path.dirname(os.path.a
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
 PBC_X, PBC_Y, PBC_Z = 1, 2, 4
 ACCUMULATE = 1
+TUNE_FORCE = 1
 
 _NAMES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOMEM: "ENOMEM", EHIP: "EHIP", ESTATE: "ESTATE"}
 
@@ -30,6 +31,10 @@ _SIGS = {
                            ctypes.POINTER(ctypes.c_size_t)],
     "demag_field_batch": [_vp, _vp, _vp, _flt, _vp, _uint, _vp, _vp],
     "demag_backward_batch": [_vp, _vp, _vp, _flt, _vp, _vp, _vp, _uint, _vp],
+    "demag_schedule_count": [_vp, ctypes.POINTER(_int)],
+    "demag_get_schedule": [_vp, _int, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int)],
+    "demag_set_schedule": [_vp, _int, _int, _int, _int],
+    "demag_autotune": [_vp, _vp, _vp, ctypes.c_char_p, _uint, ctypes.POINTER(_int), _vp],
     "demag_destroy": [_vp],
 }
 

@@ -180,3 +180,96 @@ def test_coupled_group_validation(lib):
     assert lib.demag_setup_batch(ctypes.byref(p), 3, dims9, ok_cells, origins, groups, 0, 0) == L.EUNSUPPORTED
     # groups without origins
     assert lib.demag_setup_batch(ctypes.byref(p), 3, dims, ok_cells, None, groups, 0, 0) == L.EINVAL
+
+
+def _sched(lib, p, part):
+    yg, kw, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    rc = lib.demag_get_schedule(p, part, ctypes.byref(yg), ctypes.byref(kw), ctypes.byref(r))
+    return rc, (yg.value, kw.value, r.value)
+
+
+def test_schedule_defaults_and_parts(lib):
+    rc, p = setup(lib, 512, 512, 16, 2e-9, 2e-9, 1e-9, 0, 0)
+    assert rc == L.OK
+    n = ctypes.c_int()
+    assert lib.demag_schedule_count(p, ctypes.byref(n)) == L.OK and n.value == 1
+    rc, s = _sched(lib, p, 0)
+    # 16 rows of one y line fill a 512-thread workgroup; Ny/2 = 512 points per y line at radix 8
+    assert rc == L.OK and s == (1, 4, 8)
+    assert _sched(lib, p, 1)[0] == L.EINVAL
+    assert _sched(lib, p, -1)[0] == L.EINVAL
+    lib.demag_destroy(p)
+    # batch: two geometries of independent meshes, then one coupled group
+    k = 4
+    dims = (ctypes.c_int * (3 * k))(64, 64, 1, 32, 32, 2, 64, 64, 1, 64, 64, 2)
+    cells = (ctypes.c_double * (3 * k))(*([1e-9] * (3 * k)))
+    orig = (ctypes.c_double * (3 * k))(*([0.0] * 9 + [0.0, 0.0, 5e-9]))
+    grp = (ctypes.c_int * k)(-1, -1, 0, 0)
+    p = ctypes.c_void_p()
+    assert lib.demag_setup_batch(ctypes.byref(p), k, dims, cells, orig, grp, 0, 0) == L.OK
+    assert lib.demag_schedule_count(p, ctypes.byref(n)) == L.OK and n.value == 3
+    assert _sched(lib, p, 2)[1][0] == 0   # coupled groups have no x-pass rows to tune
+    lib.demag_destroy(p)
+
+
+@pytest.mark.parametrize("n,yg,kw,radix,code", [
+    ((512, 512, 16), 0, 2, 0, L.OK),
+    ((512, 512, 16), 0, 8, 16, L.OK),        # 2 x 8 lines x 32 lanes = 512 threads
+    ((512, 512, 16), 2, 0, 0, L.OK),         # two 16-row y lines in 144 KiB of LDS
+    ((512, 512, 16), 3, 0, 0, L.EINVAL),     # beyond 160 KiB
+    ((512, 512, 16), 0, 3, 0, L.EINVAL),
+    ((512, 512, 16), 0, 0, 4, L.EUNSUPPORTED),   # 128 lanes per 512-point line
+    ((512, 512, 16), 0, 0, 32, L.EUNSUPPORTED),
+    ((200, 200, 2), 0, 8, 4, L.OK),          # 256-point lines at radix 4: 1024 threads
+    ((200, 200, 2), 0, 0, 16, L.OK),
+    ((200, 200, 2), 201, 0, 0, L.EINVAL),    # more rows than ny
+    ((100, 1000, 1), 0, 8, 0, L.EUNSUPPORTED),   # 1024-point lines at radix 16 with 8 lines
+    ((100, 1000, 1), 0, 0, 8, L.EUNSUPPORTED),
+    ((64, 64, 1), 0, 0, 16, L.EUNSUPPORTED),
+])
+def test_set_schedule_validation(lib, n, yg, kw, radix, code):
+    rc, p = setup(lib, *n, 1e-9, 1e-9, 1e-9, 0, 0)
+    assert rc == L.OK
+    before = _sched(lib, p, 0)[1]
+    rc = lib.demag_set_schedule(p, 0, yg, kw, radix)
+    assert rc == code, lib.demag_last_error()
+    after = _sched(lib, p, 0)[1]
+    if code == L.OK:
+        want = tuple(v if v else b for v, b in zip((yg, kw, radix), before))
+        assert after == want
+    else:
+        assert after == before and len(lib.demag_last_error()) > 0
+    lib.demag_destroy(p)
+
+
+def test_set_schedule_group_rules(lib):
+    k = 2
+    dims = (ctypes.c_int * (3 * k))(64, 64, 1, 64, 64, 1)
+    cells = (ctypes.c_double * (3 * k))(*([1e-9] * (3 * k)))
+    orig = (ctypes.c_double * (3 * k))(0.0, 0.0, 0.0, 0.0, 0.0, 3e-9)
+    grp = (ctypes.c_int * k)(0, 0)
+    p = ctypes.c_void_p()
+    assert lib.demag_setup_batch(ctypes.byref(p), k, dims, cells, orig, grp, 0, 0) == L.OK
+    assert lib.demag_set_schedule(p, 0, 1, 0, 0) == L.EINVAL
+    assert lib.demag_set_schedule(p, 0, 0, 2, 0) == L.OK
+    assert _sched(lib, p, 0)[1][1] == 2
+    assert lib.demag_set_schedule(p, 1, 0, 4, 0) == L.EINVAL
+    assert lib.demag_set_schedule(None, 0, 0, 4, 0) == L.EINVAL
+    lib.demag_destroy(p)
+
+
+def test_autotune_host_checks(lib, tmp_path):
+    rc, p = setup(lib, 64, 64, 1, 5e-9, 5e-9, 3e-9, 0, 0)
+    assert rc == L.OK
+    n = ctypes.c_int(7)
+    assert lib.demag_autotune(None, None, None, None, 0, ctypes.byref(n), None) == L.EINVAL
+    assert lib.demag_autotune(p, None, None, None, 2, ctypes.byref(n), None) == L.EINVAL
+    for bad in ('{"entries": {}}', '{"format": "demag-schedule-cache/1", "entries": [1]}', "{", "[]",
+                '{"format": "demag-schedule-cache/1", "entries": {"k": {"kw": }}}',
+                '{"format": "demag-schedule-cache/1"} trailing'):
+        f = tmp_path / "bad.json"
+        f.write_text(bad)
+        assert lib.demag_autotune(p, None, None, str(f).encode(), 0, ctypes.byref(n), None) == L.EINVAL, bad
+        assert b"schedule cache" in lib.demag_last_error()
+    assert n.value == 0
+    lib.demag_destroy(p)
