@@ -25,6 +25,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue: each of the 256 compute units issues one wave64 VALU
+# instruction per clock (four SIMDs, 16 lanes, 4 cycles per instruction) at
+# 2.4 GHz; packed FP32 is not used.
+VALU_INSTS_PER_S = 256 * 2.4e9
 WORKLOADS = {
     "512x512x16": dict(n=(512, 512, 16), h=(2e-9, 2e-9, 1e-9), Ms=1.1e6, seed=10),
     "1024x1024x4": dict(n=(1024, 1024, 4), h=(2e-9, 2e-9, 1e-9), Ms=1.1e6, seed=11),
@@ -48,7 +52,7 @@ def mid_pass_bytes(n):
     return 2 * spec + 6 * Kz * Ky * Kx * 4
 
 
-def bench_batch(torch, reps=10, tune=True):
+def bench_batch(torch, reps=10, tune=True, cache=None):
     """Batched multi-mesh workload: three coupled layers (512x512x2 and
     512x512x1 of 1 nm cells, 256x256x3 of 2 nm cells, 1 nm and 3 nm
     spacings) plus 64 independent 64x64x1 meshes of 5x5x3 nm cells; Ms uniform
@@ -71,7 +75,7 @@ def bench_batch(torch, reps=10, tune=True):
     plan = DemagPlan(*small)
     if tune:
         for x in (full, grp, plan):
-            x.autotune()
+            x.autotune(cache=cache)
     mf = torch.empty(full.total, dtype=torch.float32, device="cuda")
     for i, (n, _) in enumerate(meshes):
         full.view(mf, i).copy_(torch.from_numpy(inputs.unit_sphere(n, seed=100 + i)).cuda())
@@ -136,6 +140,7 @@ def main():
     ap.add_argument("--workload", default="512x512x16", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch schedules")
+    ap.add_argument("--schedule-cache", default=None, help="JSON schedule cache to apply (and extend)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
@@ -164,7 +169,7 @@ def main():
     setup_s = time.time() - t0
     t0 = time.time()
     if not args.no_tune:
-        plan.autotune()
+        plan.autotune(cache=args.schedule_cache)
     tune_s = time.time() - t0
     m = torch.from_numpy(m_np).to(dev)
     G = torch.from_numpy(G_np).to(dev)
@@ -223,6 +228,7 @@ def main():
     mid_bytes = mid_pass_bytes(n)
     achieved = mid_bytes / (pass_us["mid_y"] * 1e-6) / 1e9
     traffic = None
+    valu = None
     side = os.path.join(ROOT, "profiles", f"k_mid_{args.workload}.json")
     if os.path.exists(side):
         from paper_2008_02478_amd.profiling import source_hash
@@ -230,6 +236,12 @@ def main():
             prof = json.load(f)
         if prof.get("source_hash") == source_hash():   # counters of this very kernel build
             traffic = prof["traffic_bytes"]
+            insts = prof.get("extra_counters", {}).get("SQ_INSTS_VALU")
+            if insts:
+                floor_us = insts / VALU_INSTS_PER_S * 1e6
+                valu = {"insts_per_launch": insts, "issue_floor_us": floor_us,
+                        "issue_frac": floor_us / pass_us["mid_y"],
+                        "lds_bank_conflict_cycles": prof["extra_counters"].get("SQ_LDS_BANK_CONFLICT")}
 
     out = {
         "metric": "demag field evals/sec and cell-updates/s (fwd+bwd) at 512x512x16 FP32; HBM GB/s",
@@ -263,10 +275,11 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "algorithmic_bytes_per_launch": mid_bytes,
+            "valu": valu,
         },
     }
 
-    out["batched_multi_mesh"] = bench_batch(torch, tune=not args.no_tune)
+    out["batched_multi_mesh"] = bench_batch(torch, tune=not args.no_tune, cache=args.schedule_cache)
 
     if not args.no_cpu_baseline:
         from oracle import conv

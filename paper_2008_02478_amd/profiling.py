@@ -3,13 +3,16 @@ repository (kernel time, and HBM bytes from FETCH_SIZE / WRITE_SIZE scaled by
 the same counters read for a plain copy of known size).
 
     python -m paper_2008_02478_amd.profiling --trace T --fetch F --write W \\
-        --cal-fetch CF --cal-write CW --cal-mib 256 --kernel k_mid \\
-        --algorithmic-bytes B --command "..." --out profiles/x.md
+        --cal-fetch CF --cal-write CW --cal-mib 256 --kernel 'k_mid<10, 4, (true|false), 0' \\
+        --label k_mid --algorithmic-bytes B --command "..." --out profiles/x.md [--extra D ...]
 
 T, F, W, CF, CW are rocprofv3 output directories (csv format) of the
-kernel-trace run and of the four counter runs.  Writes a Markdown summary
-and a JSON sidecar with the per-launch figures and a hash of the kernel
-sources, so stale counter data can be recognised.
+kernel-trace run and of the four counter runs; each --extra D is one more
+counter run whose counters are listed per launch.  --kernel is a regular
+expression over kernel names; all matching kernels are combined, weighted by
+their call counts.  Writes a Markdown summary and a JSON sidecar with the
+per-launch figures and a hash of the kernel sources, so stale counter data
+can be recognised.
 """
 import argparse
 import csv
@@ -17,6 +20,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import statistics
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -39,15 +43,26 @@ def _csv(d, suffix):
 
 
 def counter_mean(d, counter, match):
+    rx = re.compile(match)
     vals = [float(r["Counter_Value"]) for r in _csv(d, "counter_collection.csv")
-            if r["Counter_Name"] == counter and match in r["Kernel_Name"]]
+            if r["Counter_Name"] == counter and rx.search(r["Kernel_Name"])]
+    if not vals:
+        raise ValueError(f"no {counter} samples for /{match}/ under {d}")
     return statistics.mean(vals), len(vals)
+
+
+def counters_in(d, match):
+    rx = re.compile(match)
+    names = sorted({r["Counter_Name"] for r in _csv(d, "counter_collection.csv") if rx.search(r["Kernel_Name"])})
+    return {n: counter_mean(d, n, match) for n in names}
 
 
 def main():
     ap = argparse.ArgumentParser()
     for k in ("trace", "fetch", "write", "cal_fetch", "cal_write", "kernel", "command", "out"):
         ap.add_argument("--" + k.replace("_", "-"), required=True)
+    ap.add_argument("--label", default=None)
+    ap.add_argument("--extra", action="append", default=[])
     ap.add_argument("--cal-mib", type=float, default=256.0)
     ap.add_argument("--algorithmic-bytes", type=float, required=True)
     ap.add_argument("--workload", default="")
@@ -64,10 +79,17 @@ def main():
     wk, nw = counter_mean(a.write, "WRITE_SIZE", a.kernel)
     read_b = fk * 1024.0 * f_scale
     write_b = wk * 1024.0 * w_scale
-    krow = [r for r in rows if a.kernel in r["Name"]]
-    avg_ns = float(krow[0]["AverageNs"]) if krow else float("nan")
+    rx = re.compile(a.kernel)
+    krow = [r for r in rows if rx.search(r["Name"])]
+    calls = sum(int(r["Calls"]) for r in krow)
+    avg_ns = (sum(float(r["AverageNs"]) * int(r["Calls"]) for r in krow) / calls) if calls else float("nan")
+    label = a.label or a.kernel
+    extra = {}
+    for d in a.extra:
+        extra.update({k: v[0] for k, v in counters_in(d, a.kernel).items()})
     out = {
-        "kernel": a.kernel, "workload": a.workload, "command": a.command,
+        "kernel": label, "kernel_regex": a.kernel, "workload": a.workload, "command": a.command,
+        "calls_in_trace": calls, "kernels": [r["Name"] for r in krow], "extra_counters": extra,
         "avg_duration_us": avg_ns / 1e3,
         "fetch_scale": f_scale, "write_scale": w_scale,
         "hbm_read_bytes": read_b, "hbm_write_bytes": write_b, "traffic_bytes": read_b + write_b,
@@ -75,7 +97,7 @@ def main():
         "achieved_GBs_algorithmic": a.algorithmic_bytes / (avg_ns * 1e-9) / 1e9,
         "source_hash": source_hash(),
     }
-    lines = [f"# {a.kernel} — {a.workload}", "", "Command (run from the repository root on the GPU box):", "",
+    lines = [f"# {label} — {a.workload}", "", "Command (run from the repository root on the GPU box):", "",
              "```", a.command, "```", "", "## Kernel trace (rocprofv3 --kernel-trace --stats)", "",
              "| kernel | calls | avg µs | min µs | max µs | % |", "|---|---|---|---|---|---|"]
     for r in rows:
@@ -85,12 +107,17 @@ def main():
               f"- calibration: a {a.cal_mib:g} MiB device copy reads FETCH_SIZE = {cf:.0f} KiB and "
               f"WRITE_SIZE = {cw:.0f} KiB per dispatch, so read bytes = {f_scale:.3f} x FETCH_SIZE KiB x 1024, "
               f"write bytes = {w_scale:.3f} x WRITE_SIZE KiB x 1024",
-              f"- {a.kernel}: FETCH_SIZE {fk:.0f} KiB ({nf} dispatches), WRITE_SIZE {wk:.0f} KiB ({nw} dispatches)",
+              f"- {label} (kernels matching `{a.kernel}`: {', '.join(r['Name'] for r in krow)}; {calls} calls "
+              f"in the trace): FETCH_SIZE {fk:.0f} KiB ({nf} dispatches), WRITE_SIZE {wk:.0f} KiB ({nw} dispatches)",
               f"- HBM read {read_b/1e6:.1f} MB + write {write_b/1e6:.1f} MB = {(read_b+write_b)/1e6:.1f} MB "
               f"per launch; algorithmic {a.algorithmic_bytes/1e6:.1f} MB",
               f"- average duration {avg_ns/1e3:.1f} µs -> {out['achieved_GBs_algorithmic']:.0f} GB/s algorithmic "
               f"({out['achieved_GBs_algorithmic']/8000:.1%} of 8 TB/s)",
               f"- kernel sources hash {out['source_hash']}", ""]
+    if extra:
+        lines += ["## Other counters, mean per launch (one rocprofv3 --pmc run each)", ""]
+        lines += [f"- {k}: {v:.4g}" for k, v in sorted(extra.items())]
+        lines.append("")
     with open(a.out, "w") as f:
         f.write("\n".join(lines))
     with open(os.path.splitext(a.out)[0] + ".json", "w") as f:
