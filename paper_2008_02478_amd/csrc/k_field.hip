@@ -191,7 +191,7 @@ k_mid(MidArgs a) {
     if (ENERGY && tid == 0) a.epart[lg] = 0.0;
     return;
   }
-  float2* stage = smem;                     // ny * KW points
+  float2* stage = smem;                     // 3 components x ny * KW points
   float2* scr = smem + (size_t)job * lds_points<M, R>();   // per-job scratch (aliases stage)
   const size_t cstride = (size_t)a.Nz * a.nTiles * ny * TILE;
   float2* blk0 = a.T + ((size_t)kz * a.nTiles + tile) * ny * TILE + half * KW;
@@ -210,25 +210,41 @@ k_mid(MidArgs a) {
 #pragma unroll
       for (int j = 0; j < R; ++j) v[c][j] = valid ? a.S[sidx(c, j)] : make_float2(0.f, 0.f);
   } else {
+    // the three components' blocks are loaded at once (16-byte copies, KW/2
+    // float4 per y row of the half tile) and staged through LDS together,
+    // so a workgroup waits for memory once
+    constexpr int V = KW / 2;
+    constexpr int NYMAX = NY > 1 ? NY / 2 : 1;
+    constexpr int NTH = mid_threads(LNY, KW, R);
+    constexpr int ITER = (NYMAX * V + NTH - 1) / NTH;
+    const int nv = ny * V;
+    float4 pre[3][ITER];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      float2* blk = blk0 + c * cstride;
-      __syncthreads();
-      {
-        // 16-byte copies: KW/2 float4 per y row of the half tile
-        constexpr int V = KW / 2;
-        float4* st4 = reinterpret_cast<float4*>(stage);
-        const float4* b4 = reinterpret_cast<const float4*>(blk);
-        for (int e = tid; e < ny * V; e += blockDim.x) {
-          const int y = e / V, q = e - y * V;
-          st4[e] = b4[(unsigned)y * (TILE / 2) + q];
-        }
+      const float4* b4 = reinterpret_cast<const float4*>(blk0 + c * cstride);
+#pragma unroll
+      for (int i = 0; i < ITER; ++i) {
+        const int e = tid + i * NTH;
+        const int y = e / V, q = e - y * V;
+        pre[c][i] = e < nv ? b4[(unsigned)y * (TILE / 2) + q] : make_float4(0.f, 0.f, 0.f, 0.f);
       }
-      __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float4* st4 = reinterpret_cast<float4*>(stage + c * ny * KW);
+#pragma unroll
+      for (int i = 0; i < ITER; ++i) {
+        const int e = tid + i * NTH;
+        if (e < nv) st4[e] = pre[c][i];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         const int y = t + T * j;
-        v[c][j] = (valid && y < ny) ? stage[y * KW + w] : make_float2(0.f, 0.f);
+        v[c][j] = (valid && y < ny) ? stage[c * ny * KW + y * KW + w] : make_float2(0.f, 0.f);
       }
       if constexpr (NRES == 2) residue_twiddle<R, false>(v[c], rbase, r != 0);
     }
@@ -287,33 +303,36 @@ k_mid(MidArgs a) {
     }
   }
 
-  // sum the two residues and store
+  // sum the two residues of the three components in LDS and store
+  __syncthreads();
+  if (lane_act && r == NRES - 1) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    float2* blk = blk0 + c * cstride;
-    __syncthreads();
-    if (lane_act && r == NRES - 1) {
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         const int y = t + T * j;
-        if (y < ny) stage[y * KW + w] = v[c][j];
+        if (y < ny) stage[c * ny * KW + y * KW + w] = v[c][j];
       }
-    }
-    __syncthreads();
-    if constexpr (NRES == 2) {
-      if (lane_act && r == 0) {
+  }
+  __syncthreads();
+  if constexpr (NRES == 2) {
+    if (lane_act && r == 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int j = 0; j < R; ++j) {
           const int y = t + T * j;
-          if (y < ny) stage[y * KW + w] = cadd(stage[y * KW + w], v[c][j]);
+          if (y < ny) stage[c * ny * KW + y * KW + w] = cadd(stage[c * ny * KW + y * KW + w], v[c][j]);
         }
-      }
-      __syncthreads();
     }
-    {
-      constexpr int V = KW / 2;
-      const float4* st4 = reinterpret_cast<const float4*>(stage);
-      float4* b4 = reinterpret_cast<float4*>(blk);
+    __syncthreads();
+  }
+  {
+    constexpr int V = KW / 2;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float4* st4 = reinterpret_cast<const float4*>(stage + c * ny * KW);
+      float4* b4 = reinterpret_cast<float4*>(blk0 + c * cstride);
       for (int q = tid; q < ny * V; q += blockDim.x) {
         const int y = q / V, s2 = q - y * V;
         b4[(unsigned)y * (TILE / 2) + s2] = st4[q];
@@ -546,7 +565,7 @@ static hipError_t mid_launch(const Geom& g, const MidArgs& a, hipStream_t s) {
   constexpr int M = NY > 1 ? NY / 2 : 1;
   constexpr int NRES = NY > 1 ? 2 : 1;
   size_t lds = (size_t)NRES * KW * lds_points<M, R>() * sizeof(float2);
-  const size_t st = (size_t)g.ny * KW * sizeof(float2);
+  const size_t st = (size_t)3 * g.ny * KW * sizeof(float2);   // staging of the three components
   if (st > lds) lds = st;
   lds += tab_points<M, R>() * sizeof(float2);
   hipError_t e = prep_lds(k_mid<LNY, KW, ENERGY, MODE, R>, lds);
