@@ -149,6 +149,7 @@ int make_geom(int nx, int ny, int nz, double dx, double dy, double dz, Geom& g, 
   g.Kx = g.Nx > 1 ? g.Nx / 2 + 1 : 1;
   g.Kyh = g.Ny > 1 ? g.Ny / 2 + 1 : 1;
   g.Kzh = g.Nz > 1 ? g.Nz / 2 + 1 : 1;
+  g.Kyp = kernel_row_pitch(g.Ny);
   g.nTiles = (g.Kx + TILE - 1) / TILE;
   g.dx = dx; g.dy = dy; g.dz = dz;
   const size_t pitch_bytes = (size_t)xrow_pitch_rt(g.lnx) * sizeof(float2);
@@ -177,7 +178,7 @@ void layout(demag_plan* p) {
     const Geom& g = s.g;
     const size_t nb = s.members.size();
     s.k_off = kb;
-    kb += align256((size_t)6 * g.Kzh * g.Kyh * g.Kx * sizeof(float));
+    kb += align256((size_t)6 * g.Kzh * g.Kyp * g.Kx * sizeof(float));
     s.tab_off = kb;
     kb += align256(nb * sizeof(long long)) + align256(nb * sizeof(int));
     s.t_off = wb;
@@ -270,6 +271,7 @@ int make_group(const std::vector<int>& idx, const int* dims, const double* cells
   g.Kx = g.Nx / 2 + 1;
   g.Kyh = g.Ny > 1 ? g.Ny / 2 + 1 : 1;
   g.Kzh = 1;
+  g.Kyp = kernel_row_pitch(g.Ny);
   g.nTiles = (g.Kx + TILE - 1) / TILE;
   g.dx = fx; g.dy = fy; g.dz = 1.0;
   g.yg = 1;

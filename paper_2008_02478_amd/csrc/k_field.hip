@@ -198,6 +198,18 @@ k_mid(MidArgs a) {
 
   if constexpr (M > R) fill_stage_table<M, R>(tab, a.tw, tid, blockDim.x);
   const float2 rbase = twiddle<false>(a.tw, t, ilog2(2 * M));
+
+  // The kernel spectrum of this workgroup (KW consecutive kx lines of 6 rows
+  // of KYP floats, contiguous in K[kz][kx][c][ky]) is requested here and
+  // held in registers through the forward transforms, so its latency
+  // overlaps them; it moves to LDS just before the product.
+  constexpr int KYP = kernel_row_pitch(NY);
+  constexpr int NTHK = mid_threads(LNY, KW, R);
+  constexpr int KF4 = KW * 6 * KYP / 4;           // float4 per workgroup block
+  constexpr int KIT = MODE == 0 ? (KF4 + NTHK - 1) / NTHK : 1;
+  const int kzf = (kz <= a.Nz / 2) ? kz : a.Nz - kz;
+  const int kx0 = tile * TILE + half * KW;
+  float4 kp[KIT];
   __syncthreads();   // stage table complete before any FFT reads it
   float2 v[3][R];
   // S index of (c, kz, kx, residue r, k') in MODE 1 / 2
@@ -227,6 +239,17 @@ k_mid(MidArgs a) {
         const int e = tid + i * NTH;
         const int y = e / V, q = e - y * V;
         pre[c][i] = e < nv ? b4[(unsigned)y * (TILE / 2) + q] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+    // kernel rows after the components: waits for the components then leave
+    // the kernel rows in flight (memory counters retire in issue order)
+    if constexpr (MODE == 0) {
+      const float4* Kb4 = reinterpret_cast<const float4*>(a.K + ((size_t)kzf * a.Kx + kx0) * 6 * KYP);
+#pragma unroll
+      for (int i = 0; i < KIT; ++i) {
+        const int e = tid + i * NTHK;
+        const bool in = e < KF4 && kx0 + e / (6 * KYP / 4) < a.Kx;
+        kp[i] = in ? Kb4[e] : make_float4(0.f, 0.f, 0.f, 0.f);
       }
     }
 #pragma unroll
@@ -264,13 +287,32 @@ k_mid(MidArgs a) {
     }
   }
 
-  // point-wise product with the real, symmetric kernel spectrum
+  // point-wise product with the real, symmetric kernel spectrum.  In LDS each
+  // kernel row is split by the parity of ky (the parity of a job's folded ky
+  // is its residue r), so the lanes of a job read consecutive words.
+  float* const kl = reinterpret_cast<float*>(smem);   // aliases stage and FFT scratch
+  if constexpr (MODE == 0) {
+    __syncthreads();   // every job is done with its forward FFT scratch
+#pragma unroll
+    for (int i = 0; i < KIT; ++i) {
+      const int e = tid + i * NTHK;
+      if (e < KF4) {
+        const int row = (4 * e) / KYP, ky0 = 4 * e - row * KYP;
+        float* const dst = kl + row * KYP;
+        if constexpr (NRES == 2) {
+          *reinterpret_cast<float2*>(dst + ky0 / 2) = make_float2(kp[i].x, kp[i].z);
+          *reinterpret_cast<float2*>(dst + KYP / 2 + ky0 / 2) = make_float2(kp[i].y, kp[i].w);
+        } else {
+          *reinterpret_cast<float4*>(dst + ky0) = kp[i];
+        }
+      }
+    }
+    __syncthreads();
+  }
   double e = 0.0;
   if (lane_act && MODE == 0) {
-    const int kzf = (kz <= a.Nz / 2) ? kz : a.Nz - kz;
     const float sz = (kz <= a.Nz / 2) ? 1.f : -1.f;
-    const int kxc = min(kx, a.Kx - 1);
-    const float* Kb = a.K + ((size_t)kzf * a.Kx + kxc) * 6 * a.Kyh;
+    const float* const Kb = kl + w * 6 * KYP;
     const float wkx = (kx == 0 || 2 * kx == a.Nx) ? 1.f : 2.f;
     float ef = 0.f;
 #pragma unroll
@@ -278,13 +320,14 @@ k_mid(MidArgs a) {
       const int ky = NRES * (t + T * j) + r;
       const bool lo = 2 * ky <= NY;
       const int kyf = lo ? ky : NY - ky;
+      const int ki = NRES == 2 ? r * (KYP / 2) + (kyf >> 1) : kyf;
       const float sy = lo ? 1.f : -1.f;
-      const float kxx = Kb[0 * a.Kyh + kyf];
-      const float kyy = Kb[1 * a.Kyh + kyf];
-      const float kzz = Kb[2 * a.Kyh + kyf];
-      const float kxy = sy * Kb[3 * a.Kyh + kyf];
-      const float kxz = sz * Kb[4 * a.Kyh + kyf];
-      const float kyz = sy * sz * Kb[5 * a.Kyh + kyf];
+      const float kxx = Kb[0 * KYP + ki];
+      const float kyy = Kb[1 * KYP + ki];
+      const float kzz = Kb[2 * KYP + ki];
+      const float kxy = sy * Kb[3 * KYP + ki];
+      const float kxz = sz * Kb[4 * KYP + ki];
+      const float kyz = sy * sz * Kb[5 * KYP + ki];
       const float2 mx = v[0][j], my = v[1][j], mz = v[2][j];
       const float2 hx = make_float2(kxx * mx.x + kxy * my.x + kxz * mz.x, kxx * mx.y + kxy * my.y + kxz * mz.y);
       const float2 hy = make_float2(kxy * mx.x + kyy * my.x + kyz * mz.x, kxy * mx.y + kyy * my.y + kyz * mz.y);
@@ -295,6 +338,7 @@ k_mid(MidArgs a) {
     }
     if (ENERGY && valid) e = (double)(wkx * ef);
   }
+  if constexpr (MODE == 0) __syncthreads();   // kernel rows read before the scratch is reused
   if (lane_act) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -567,6 +611,8 @@ static hipError_t mid_launch(const Geom& g, const MidArgs& a, hipStream_t s) {
   size_t lds = (size_t)NRES * KW * lds_points<M, R>() * sizeof(float2);
   const size_t st = (size_t)3 * g.ny * KW * sizeof(float2);   // staging of the three components
   if (st > lds) lds = st;
+  const size_t kr = MODE == 0 ? (size_t)KW * 6 * kernel_row_pitch(NY) * sizeof(float) : 0;   // kernel rows
+  if (kr > lds) lds = kr;
   lds += tab_points<M, R>() * sizeof(float2);
   hipError_t e = prep_lds(k_mid<LNY, KW, ENERGY, MODE, R>, lds);
   if (e != hipSuccess) return e;

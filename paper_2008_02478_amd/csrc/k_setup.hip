@@ -149,21 +149,22 @@ __global__ void k_axis(const double* __restrict__ in, double* __restrict__ out, 
   out[idx] = acc;
 }
 
-// in [6][Kzh][Kyh][Kx] (FP64) -> K[kz][kx][c][ky] (FP32) times -sign_c / npad
-__global__ void k_pack(const double* __restrict__ in, float* __restrict__ K, int Kx, int Kyh, int Kzh,
+// in [6][Kzh][Kyh][Kx] (FP64) -> K[kz][kx][c][ky] (FP32, row pitch Kyp,
+// zero padding past Kyh) times -sign_c / npad
+__global__ void k_pack(const double* __restrict__ in, float* __restrict__ K, int Kx, int Kyh, int Kyp, int Kzh,
                        double inv_npad) {
   const size_t per_c = (size_t)Kzh * Kyh * Kx;
-  const size_t tot = 6 * per_c;
+  const size_t tot = (size_t)6 * Kzh * Kyp * Kx;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= tot) return;
-  const int ky = (int)(idx % Kyh);
-  size_t rem = idx / Kyh;
+  const int ky = (int)(idx % Kyp);
+  size_t rem = idx / Kyp;
   const int c = (int)(rem % 6);
   rem /= 6;
   const int kx = (int)(rem % Kx);
   const int kz = (int)(rem / Kx);
   const double s = (c < 3 ? -1.0 : 1.0) * inv_npad;
-  K[idx] = (float)(s * in[c * per_c + ((size_t)kz * Kyh + ky) * Kx + kx]);
+  K[idx] = ky < Kyh ? (float)(s * in[c * per_c + ((size_t)kz * Kyh + ky) * Kx + kx]) : 0.f;
 }
 
 }  // namespace demag
@@ -338,8 +339,8 @@ hipError_t launch_axis(const double* in, double* out, int outer, int nin, int no
 }
 
 hipError_t launch_pack(const double* in, float* K, const Geom& g, hipStream_t s) {
-  const size_t tot = (size_t)6 * g.Kzh * g.Kyh * g.Kx;
-  hipLaunchKernelGGL(k_pack, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, in, K, g.Kx, g.Kyh, g.Kzh,
+  const size_t tot = (size_t)6 * g.Kzh * g.Kyp * g.Kx;
+  hipLaunchKernelGGL(k_pack, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, in, K, g.Kx, g.Kyh, g.Kyp, g.Kzh,
                      1.0 / ((double)g.Nx * g.Ny * g.Nz));
   return hipGetLastError();
 }
