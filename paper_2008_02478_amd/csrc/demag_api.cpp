@@ -178,7 +178,7 @@ void layout(demag_plan* p) {
     const Geom& g = s.g;
     const size_t nb = s.members.size();
     s.k_off = kb;
-    kb += align256((size_t)6 * g.Kzh * g.Kyp * g.Kx * sizeof(float));
+    kb += align256((size_t)6 * g.Kzh * g.Kx * (g.Kyp + 1) * sizeof(float));   // rows, then KN
     s.tab_off = kb;
     kb += align256(nb * sizeof(long long)) + align256(nb * sizeof(int));
     s.t_off = wb;

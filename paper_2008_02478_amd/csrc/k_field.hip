@@ -66,23 +66,19 @@ __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_e
     }
   } else {
     const bool even = (nx & 1) == 0;
+    const float* const mc = a.m + (size_t)c * nz * ny * nx;
     xfwd_rows<LNX, FWD_THREADS>(smem, tab, a.tw, rows, PITCH, [&](int row, int mm) -> float2 {
       const int yl = row / nz, z = row - yl * nz;
-      const size_t off = ((size_t)z * ny + (y0 + yl)) * nx;
-      const float* src = a.m + (size_t)c * nz * ny * nx + off;
-      const float* msr = a.Ms ? a.Ms + off : nullptr;
+      const float* src = mc + ((size_t)z * ny + (y0 + yl)) * nx;
       const int xi = 2 * mm;
-      if (even) {
-        // even rows: (x[2m], x[2m+1]) is one aligned float2
-        if (xi >= nx) return make_float2(0.f, 0.f);
-        const float2 v = reinterpret_cast<const float2*>(src)[mm];
-        const float2 s2 = msr ? reinterpret_cast<const float2*>(msr)[mm] : make_float2(a.ms, a.ms);
-        return make_float2(v.x * s2.x, v.y * s2.y);
-      }
-      float v0 = 0.f, v1 = 0.f;
-      if (xi < nx) v0 = src[xi] * (msr ? msr[xi] : a.ms);
-      if (xi + 1 < nx) v1 = src[xi + 1] * (msr ? msr[xi + 1] : a.ms);
-      return make_float2(v0, v1);
+      if (even) return xi < nx ? reinterpret_cast<const float2*>(src)[mm] : make_float2(0.f, 0.f);
+      return make_float2(xi < nx ? src[xi] : 0.f, xi + 1 < nx ? src[xi + 1] : 0.f);
+    }, [&](int row, int mm, float2 v) -> float2 {
+      if (!a.Ms) return make_float2(v.x * a.ms, v.y * a.ms);
+      const int yl = row / nz, z = row - yl * nz;
+      const float* msr = a.Ms + ((size_t)z * ny + (y0 + yl)) * nx;
+      const int xi = 2 * mm;
+      return make_float2(xi < nx ? v.x * msr[xi] : 0.f, xi + 1 < nx ? v.y * msr[xi + 1] : 0.f);
     });
   }
   __syncthreads();
@@ -200,16 +196,21 @@ k_mid(MidArgs a) {
   const float2 rbase = twiddle<false>(a.tw, t, ilog2(2 * M));
 
   // The kernel spectrum of this workgroup (KW consecutive kx lines of 6 rows
-  // of KYP floats, contiguous in K[kz][kx][c][ky]) is requested here and
-  // held in registers through the forward transforms, so its latency
-  // overlaps them; it moves to LDS just before the product.
+  // of KYP floats, contiguous in K[kz][kx][c][ky], plus their 6 KW Nyquist
+  // entries) is requested with the components and held in registers through
+  // the forward transforms, so its latency overlaps them; it moves to LDS
+  // just before the product.  In LDS a row (pitch KLP) holds the even-ky
+  // half, the Nyquist entry at KYP/2, and the odd-ky half from OH.
   constexpr int KYP = kernel_row_pitch(NY);
+  constexpr int KLP = NRES == 2 ? KYP + 4 : KYP;
+  constexpr int OH = KYP / 2 + 2;
   constexpr int NTHK = mid_threads(LNY, KW, R);
   constexpr int KF4 = KW * 6 * KYP / 4;           // float4 per workgroup block
   constexpr int KIT = MODE == 0 ? (KF4 + NTHK - 1) / NTHK : 1;
   const int kzf = (kz <= a.Nz / 2) ? kz : a.Nz - kz;
   const int kx0 = tile * TILE + half * KW;
   float4 kp[KIT];
+  float knv = 0.f;
   __syncthreads();   // stage table complete before any FFT reads it
   float2 v[3][R];
   // S index of (c, kz, kx, residue r, k') in MODE 1 / 2
@@ -251,6 +252,8 @@ k_mid(MidArgs a) {
         const bool in = e < KF4 && kx0 + e / (6 * KYP / 4) < a.Kx;
         kp[i] = in ? Kb4[e] : make_float4(0.f, 0.f, 0.f, 0.f);
       }
+      if (NY >= 4 && tid < 6 * KW && kx0 + tid / 6 < a.Kx)
+        knv = a.K[(size_t)6 * a.Kzh * a.Kx * KYP + ((size_t)kzf * a.Kx + kx0) * 6 + tid];
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -298,21 +301,22 @@ k_mid(MidArgs a) {
       const int e = tid + i * NTHK;
       if (e < KF4) {
         const int row = (4 * e) / KYP, ky0 = 4 * e - row * KYP;
-        float* const dst = kl + row * KYP;
+        float* const dst = kl + row * KLP;
         if constexpr (NRES == 2) {
           *reinterpret_cast<float2*>(dst + ky0 / 2) = make_float2(kp[i].x, kp[i].z);
-          *reinterpret_cast<float2*>(dst + KYP / 2 + ky0 / 2) = make_float2(kp[i].y, kp[i].w);
+          *reinterpret_cast<float2*>(dst + OH + ky0 / 2) = make_float2(kp[i].y, kp[i].w);
         } else {
           *reinterpret_cast<float4*>(dst + ky0) = kp[i];
         }
       }
     }
+    if (NY >= 4 && tid < 6 * KW) kl[tid * KLP + KYP / 2] = knv;
     __syncthreads();
   }
   double e = 0.0;
   if (lane_act && MODE == 0) {
     const float sz = (kz <= a.Nz / 2) ? 1.f : -1.f;
-    const float* const Kb = kl + w * 6 * KYP;
+    const float* const Kb = kl + w * 6 * KLP;
     const float wkx = (kx == 0 || 2 * kx == a.Nx) ? 1.f : 2.f;
     float ef = 0.f;
 #pragma unroll
@@ -320,14 +324,18 @@ k_mid(MidArgs a) {
       const int ky = NRES * (t + T * j) + r;
       const bool lo = 2 * ky <= NY;
       const int kyf = lo ? ky : NY - ky;
-      const int ki = NRES == 2 ? r * (KYP / 2) + (kyf >> 1) : kyf;
+      // index in the LDS row: even/odd half by the residue, the Nyquist
+      // entry at KYP/2 (which the even-half index reaches by itself for
+      // Ny >= 8)
+      int ki = NRES == 2 ? (r ? OH : 0) + (kyf >> 1) : kyf;
+      if constexpr (NY == 4) ki = kyf == 2 ? KYP / 2 : ki;
       const float sy = lo ? 1.f : -1.f;
-      const float kxx = Kb[0 * KYP + ki];
-      const float kyy = Kb[1 * KYP + ki];
-      const float kzz = Kb[2 * KYP + ki];
-      const float kxy = sy * Kb[3 * KYP + ki];
-      const float kxz = sz * Kb[4 * KYP + ki];
-      const float kyz = sy * sz * Kb[5 * KYP + ki];
+      const float kxx = Kb[0 * KLP + ki];
+      const float kyy = Kb[1 * KLP + ki];
+      const float kzz = Kb[2 * KLP + ki];
+      const float kxy = sy * Kb[3 * KLP + ki];
+      const float kxz = sz * Kb[4 * KLP + ki];
+      const float kyz = sy * sz * Kb[5 * KLP + ki];
       const float2 mx = v[0][j], my = v[1][j], mz = v[2][j];
       const float2 hx = make_float2(kxx * mx.x + kxy * my.x + kxz * mz.x, kxx * mx.y + kxy * my.y + kxz * mz.y);
       const float2 hy = make_float2(kxy * mx.x + kyy * my.x + kyz * mz.x, kxy * mx.y + kyy * my.y + kyz * mz.y);
@@ -611,7 +619,8 @@ static hipError_t mid_launch(const Geom& g, const MidArgs& a, hipStream_t s) {
   size_t lds = (size_t)NRES * KW * lds_points<M, R>() * sizeof(float2);
   const size_t st = (size_t)3 * g.ny * KW * sizeof(float2);   // staging of the three components
   if (st > lds) lds = st;
-  const size_t kr = MODE == 0 ? (size_t)KW * 6 * kernel_row_pitch(NY) * sizeof(float) : 0;   // kernel rows
+  const size_t klp = NRES == 2 ? kernel_row_pitch(NY) + 4 : kernel_row_pitch(NY);
+  const size_t kr = MODE == 0 ? (size_t)KW * 6 * klp * sizeof(float) : 0;   // kernel rows
   if (kr > lds) lds = kr;
   lds += tab_points<M, R>() * sizeof(float2);
   hipError_t e = prep_lds(k_mid<LNY, KW, ENERGY, MODE, R>, lds);

@@ -33,14 +33,17 @@ __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_e
     const int jy = v - pi.oy;
     if (jy < 0 || jy % pi.sy != 0 || jy / pi.sy >= pi.ny) return make_float2(0.f, 0.f);
     const float* src = a.m + pi.moff + (((size_t)c * pi.nz + pi.k) * pi.ny + jy / pi.sy) * pi.nx;
-    const float sc = a.backward ? 1.0f / pi.vol : (a.ms_mesh ? a.ms_mesh[pi.gid] : a.ms);
     float val[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int ix = 2 * mm + h - pi.ox;
-      val[h] = (ix >= 0 && ix % pi.sx == 0 && ix / pi.sx < pi.nx) ? sc * src[ix / pi.sx] : 0.f;
+      val[h] = (ix >= 0 && ix % pi.sx == 0 && ix / pi.sx < pi.nx) ? src[ix / pi.sx] : 0.f;
     }
     return make_float2(val[0], val[1]);
+  }, [&](int p, int, float2 u) -> float2 {
+    const PlaneInfo& pi = a.pl[p];
+    const float sc = a.backward ? 1.0f / pi.vol : (a.ms_mesh ? a.ms_mesh[pi.gid] : a.ms);
+    return make_float2(sc * u.x, sc * u.y);
   });
   const int Kx = a.Kx;
   for (int it = threadIdx.x; it < a.P * Kx; it += FWD_THREADS) {

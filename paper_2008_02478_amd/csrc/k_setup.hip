@@ -149,22 +149,37 @@ __global__ void k_axis(const double* __restrict__ in, double* __restrict__ out, 
   out[idx] = acc;
 }
 
-// in [6][Kzh][Kyh][Kx] (FP64) -> K[kz][kx][c][ky] (FP32, row pitch Kyp,
-// zero padding past Kyh) times -sign_c / npad
+// in [6][Kzh][Kyh][Kx] (FP64) -> K[kz][kx][c][ky] (FP32, rows of pitch Kyp
+// holding ky < Ny/2, or ky = 0 for Ny = 1, zero padded) and KN[kz][kx][c]
+// (ky = Ny/2, Ny >= 4) after the rows; times -sign_c / npad
 __global__ void k_pack(const double* __restrict__ in, float* __restrict__ K, int Kx, int Kyh, int Kyp, int Kzh,
-                       double inv_npad) {
+                       int Ny, double inv_npad) {
   const size_t per_c = (size_t)Kzh * Kyh * Kx;
-  const size_t tot = (size_t)6 * Kzh * Kyp * Kx;
+  const size_t nrow = (size_t)6 * Kzh * Kyp * Kx;
+  const size_t tot = nrow + (size_t)6 * Kzh * Kx;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= tot) return;
-  const int ky = (int)(idx % Kyp);
-  size_t rem = idx / Kyp;
-  const int c = (int)(rem % 6);
-  rem /= 6;
-  const int kx = (int)(rem % Kx);
-  const int kz = (int)(rem / Kx);
+  int ky, c, kx, kz;
+  bool have;
+  if (idx < nrow) {
+    ky = (int)(idx % Kyp);
+    size_t rem = idx / Kyp;
+    c = (int)(rem % 6);
+    rem /= 6;
+    kx = (int)(rem % Kx);
+    kz = (int)(rem / Kx);
+    have = Ny >= 4 ? ky < Ny / 2 : ky == 0;
+  } else {
+    size_t rem = idx - nrow;
+    c = (int)(rem % 6);
+    rem /= 6;
+    kx = (int)(rem % Kx);
+    kz = (int)(rem / Kx);
+    ky = Ny / 2;
+    have = Ny >= 4;
+  }
   const double s = (c < 3 ? -1.0 : 1.0) * inv_npad;
-  K[idx] = ky < Kyh ? (float)(s * in[c * per_c + ((size_t)kz * Kyh + ky) * Kx + kx]) : 0.f;
+  K[idx] = have ? (float)(s * in[c * per_c + ((size_t)kz * Kyh + ky) * Kx + kx]) : 0.f;
 }
 
 }  // namespace demag
@@ -339,8 +354,8 @@ hipError_t launch_axis(const double* in, double* out, int outer, int nin, int no
 }
 
 hipError_t launch_pack(const double* in, float* K, const Geom& g, hipStream_t s) {
-  const size_t tot = (size_t)6 * g.Kzh * g.Kyp * g.Kx;
-  hipLaunchKernelGGL(k_pack, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, in, K, g.Kx, g.Kyh, g.Kyp, g.Kzh,
+  const size_t tot = (size_t)6 * g.Kzh * g.Kx * (g.Kyp + 1);
+  hipLaunchKernelGGL(k_pack, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, in, K, g.Kx, g.Kyh, g.Kyp, g.Kzh, g.Ny,
                      1.0 / ((double)g.Nx * g.Ny * g.Nz));
   return hipGetLastError();
 }

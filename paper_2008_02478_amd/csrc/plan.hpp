@@ -6,17 +6,20 @@
 
 namespace demag {
 
-constexpr int TILE = 8;          // kx points per tile of the spectrum work buffer
+constexpr int TILE = 16;         // kx points per tile of the spectrum work buffer (128-byte rows)
 constexpr int FWD_THREADS = 512;
 constexpr int INV_THREADS = 512;
 constexpr int RED_THREADS = 256;
 
 // Points per lane (R) of an M-point line FFT, and its padded LDS footprint
 // (one pad point after every 2^3 points for radix 8, 2^5 for radix 16).
-// Row pitch (floats) of the kernel spectrum K[kz][kx][component][ky] for a
-// padded y length Ny: Ny/2 + 1 rounded up to a multiple of 4, so that every
-// row starts 16-byte aligned (the padding holds zeros).
-constexpr int kernel_row_pitch(int Ny) { return (((Ny > 1 ? Ny / 2 + 1 : 1) + 3) / 4) * 4; }
+// Kernel spectrum storage for a padded y length Ny: rows K[kz][kx][component][ky]
+// of kernel_row_pitch(Ny) floats holding ky < Ny/2 (ky = 0 when Ny = 1; zero
+// padding up to the pitch), and the Nyquist entries ky = Ny/2 (Ny >= 4) in a
+// side array KN[kz][kx][component] after the rows.  The pitch is a multiple of
+// 4 floats, so rows start 16-byte aligned and a block of rows splits evenly
+// over the lanes that fetch it.
+constexpr int kernel_row_pitch(int Ny) { return Ny >= 8 ? Ny / 2 : 4; }
 
 constexpr int line_radix(int M) { return M >= 1024 ? 16 : (M >= 8 ? 8 : M); }
 constexpr int line_pad_shift(int R) { return R >= 16 ? 5 : 3; }
@@ -62,7 +65,7 @@ struct Geom {
   int lnx, lny, lnz;   // log2 of the padded lengths
   int Kx;              // Nx/2 + 1 (1 when Nx == 1): half spectrum along x
   int Kyh, Kzh;        // Ny/2 + 1, Nz/2 + 1 (1 for unit lengths): stored octant
-  int Kyp;             // row pitch of the stored kernel spectrum: Kyh rounded up to 4
+  int Kyp;             // row pitch of the stored kernel spectrum (kernel_row_pitch)
   int nTiles;          // ceil(Kx / TILE)
   int yg;              // y rows per workgroup in the x passes
   int mid_kw;          // kx lines per workgroup of the middle pass (2, 4 or 8)
@@ -137,7 +140,7 @@ struct FwdArgs {
 };
 
 struct MidArgs {
-  float2* T; const float* K; const float2* tw;  // K rows have pitch kernel_row_pitch(Ny)
+  float2* T; const float* K; const float2* tw;  // K: rows of pitch kernel_row_pitch(Ny), then KN
   double* epart;               // one partial per workgroup, or nullptr
   int ny, Nz, Nx, nTiles, Kx, Kyh, Kzh, kw_halves;
   int nb; size_t Tb; int nblk1; // workgroups per member

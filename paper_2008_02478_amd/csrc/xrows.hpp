@@ -27,11 +27,15 @@ constexpr int xtab_points() {
 }
 
 
-// load(row, m) returns (x[2m], x[2m+1]) of that row (zeros past its end).
-// On return row r of smem holds X[0..L].  Ends with a workgroup barrier.
-template <int LNX, int NTH, typename Load>
+// load(row, m) returns the raw (x[2m], x[2m+1]) of that row (zeros past its
+// end) and scale(row, m, v) the value transformed, so that a round's loads
+// can be issued one round ahead: round i + 1's loads are in flight while
+// round i is transformed.  On return row r of smem holds X[0..L].  Ends with
+// a workgroup barrier.
+template <int LNX, int NTH, typename Load, typename Scale>
 __device__ __forceinline__ void xfwd_rows(float2* __restrict__ smem, float2* __restrict__ tab,
-                                          const float2* __restrict__ tw, int rows, int pitch, Load&& load) {
+                                          const float2* __restrict__ tw, int rows, int pitch, Load&& load,
+                                          Scale&& scale) {
   constexpr int NX = 1 << LNX;
   constexpr int L = NX / 2;
   constexpr int P = L / 2;
@@ -42,6 +46,9 @@ __device__ __forceinline__ void xfwd_rows(float2* __restrict__ smem, float2* __r
   const int sub = tid / (2 * T);
   const int r = (tid / T) & 1;
   const int t = tid % T;
+  float2 nxt[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) nxt[j] = sub < rows ? load(sub, t + T * j) : make_float2(0.f, 0.f);
   fill_stage_table<P, R>(tab, tw, tid, NTH);
   const float2 rbase = twiddle<false>(tw, t, ilog2(2 * P));
   __syncthreads();
@@ -50,9 +57,15 @@ __device__ __forceinline__ void xfwd_rows(float2* __restrict__ smem, float2* __r
     const bool act = row < rows;
     float2* rb = smem + row * pitch;
     float2 u[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) u[j] = nxt[j];
+    if (row + RPR < rows) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) nxt[j] = load(row + RPR, t + T * j);
+    }
     if (act) {
 #pragma unroll
-      for (int j = 0; j < R; ++j) u[j] = load(row, t + T * j);
+      for (int j = 0; j < R; ++j) u[j] = scale(row, t + T * j, u[j]);
       residue_twiddle<R, false>(u, rbase, r != 0);
       group_fft<P, R, false>(u, rb + r * lds_points<P, R>(), t, tab);
     }
