@@ -441,15 +441,18 @@ __global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_e
       d0[0] = Tc[o];
     } else {
       constexpr int Q = NZ / 2;
-      float2 v[Q];
+      // both residues requested before either is transformed
+      float2 v[Q], w[Q];
 #pragma unroll
       for (int k = 0; k < Q; ++k) v[k] = Tc[o + (unsigned)(2 * k) * kzstride];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) w[k] = Tc[o + (unsigned)(2 * k + 1) * kzstride];
       dft<Q, true>(v);
 #pragma unroll
       for (int z = 0; z < Q; ++z)
         if (z < nz) d0[z * PITCH] = v[z];
 #pragma unroll
-      for (int k = 0; k < Q; ++k) v[k] = Tc[o + (unsigned)(2 * k + 1) * kzstride];
+      for (int k = 0; k < Q; ++k) v[k] = w[k];
       dft<Q, true>(v);
       zodd_twiddle<NZ, 0, true>(v);
 #pragma unroll
