@@ -11,6 +11,10 @@ Contents
   conv.py    H = -N * M by brute-force direct sum and by zero-padded FP64 FFT
              convolution (Sec. 7), demag energy (Appendix A field/energy
              relation), gradients of the energy and of <G, H>.
+  multilayer.py  inter-mesh tensor for unequal cells and the Eq. 4 direct sum
+             over a collection of meshes (Sec. 3).
+  pbc.py     image-summed tensor for periodic boundaries (Sec. 3, multiple
+             images).
 """
 from .newell import (COMPONENTS, newell_f, newell_g, newell_near, gl_far,
                      tensor_at, tensor_octant, tensor_full)
