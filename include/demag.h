@@ -24,9 +24,15 @@
  *    plan share its work buffer and must be ordered on one stream.
  *  - Arrays of vectors are SoA [3][nz][ny][nx], x fastest, FP32.  Lengths in
  *    metres, M and H in A/m, energies in joules (FP64).
- *  - Supported sizes: 1 <= nx <= 2048, 1 <= ny <= 1024, 1 <= nz <= 16, open
- *    boundaries (each axis zero-padded to the next power of two >= 2n-1).
- *    Periodic boundaries are reserved flags and return DEMAG_EUNSUPPORTED.
+ *  - Supported sizes: 1 <= nx <= 2048, 1 <= ny <= 1024, 1 <= nz <= 16; each
+ *    axis zero-padded to the next power of two >= 2n-1.
+ *  - Periodic boundaries (Sec. 3, multiple images): along a periodic axis a
+ *    (period L_a = n_a h_a) the mesh is repeated pbc_images times on either
+ *    side and the field is that of the repeated mesh in its central copy,
+ *    H_i = -sum_j sum_{|k_a| <= K} N(r_i - r_j - k o L) M_j.  The tensor is
+ *    summed over the images at set-up; the field passes are those of open
+ *    boundaries.  All three axes periodic sums the cube of images, a
+ *    conditionally convergent sum whose value depends on that shape.
  */
 #ifndef DEMAG_H
 #define DEMAG_H
@@ -42,7 +48,7 @@ typedef struct demag_plan demag_plan;
 enum {
   DEMAG_OK = 0,
   DEMAG_EINVAL = -1,        /* invalid argument (null pointer, bad size, NaN cell) */
-  DEMAG_EUNSUPPORTED = -2,  /* valid but not supported (size limits, periodic axes) */
+  DEMAG_EUNSUPPORTED = -2,  /* valid but not supported (size limits, periodic coupled groups) */
   DEMAG_ENOMEM = -3,        /* host or set-up device allocation failed */
   DEMAG_EHIP = -4,          /* a HIP runtime call failed */
   DEMAG_ESTATE = -5         /* wrong call order (field before bind, bind twice) */
@@ -52,9 +58,11 @@ enum { DEMAG_PBC_X = 1, DEMAG_PBC_Y = 2, DEMAG_PBC_Z = 4 };
 enum { DEMAG_ACCUMULATE = 1 };   /* H += H_d instead of H = H_d */
 
 /* Validate a mesh of nx*ny*nz cells of size dx*dy*dz metres and create a plan
- * (host memory only, no HIP call).  pbc_flags: OR of DEMAG_PBC_*; any periodic
- * axis currently returns DEMAG_EUNSUPPORTED.  pbc_images is ignored for open
- * boundaries.  On success *out owns the plan (free with demag_destroy). */
+ * (host memory only, no HIP call).  pbc_flags: OR of DEMAG_PBC_* (periodic
+ * axes); pbc_images: images K on either side of each periodic axis (<= 0: 10;
+ * more than 1000: DEMAG_EINVAL), ignored without periodic axes.  Set-up cost
+ * grows with (2K+1)^(periodic axes).  On success *out owns the plan (free
+ * with demag_destroy). */
 int demag_setup(demag_plan** out, int nx, int ny, int nz, double dx, double dy, double dz,
                 unsigned pbc_flags, int pbc_images);
 
@@ -115,7 +123,9 @@ int demag_backward(const demag_plan* plan, const float* d_G, const float* d_Ms, 
  * identical geometry share one kernel spectrum and one launch per pass.
  * Vectors of all meshes are concatenated in mesh order, each mesh SoA
  * [3][nz][ny][nx], at the float offsets given by demag_batch_layout.
- * Periodic flags return DEMAG_EUNSUPPORTED.  Host only, like demag_setup. */
+ * pbc_flags / pbc_images apply to every independent mesh as in demag_setup;
+ * with periodic axes, coupled groups return DEMAG_EUNSUPPORTED.  Host only,
+ * like demag_setup. */
 int demag_setup_batch(demag_plan** out, int nmesh, const int* dims, const double* cells, const double* origins,
                       const int* groups, unsigned pbc_flags, int pbc_images);
 

@@ -136,7 +136,11 @@ void gauss_legendre(int n, double* x, double* w) {
 bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255) == 0; }
 
 // Validate one mesh and derive its geometry (host only).
-int make_geom(int nx, int ny, int nz, double dx, double dy, double dz, Geom& g, const char* who) {
+constexpr int DEFAULT_IMAGES = 10;
+constexpr int MAX_IMAGES = 1000;
+
+int make_geom(int nx, int ny, int nz, double dx, double dy, double dz, unsigned pbc, int images, Geom& g,
+              const char* who) {
   if (nx < 1 || ny < 1 || nz < 1) return fail(DEMAG_EINVAL, std::string(who) + ": mesh dimensions must be >= 1");
   if (!(std::isfinite(dx) && std::isfinite(dy) && std::isfinite(dz)) || dx <= 0 || dy <= 0 || dz <= 0)
     return fail(DEMAG_EINVAL, std::string(who) + ": cell sizes must be finite and > 0");
@@ -167,6 +171,8 @@ int make_geom(int nx, int ny, int nz, double dx, double dy, double dz, Geom& g, 
   g.yg = yg;
   g.mid_kw = 4;
   g.mid_r = 0;
+  g.pbc = pbc;
+  g.images = pbc ? (images > 0 ? images : DEFAULT_IMAGES) : 0;
   return DEMAG_OK;
 }
 
@@ -277,6 +283,8 @@ int make_group(const std::vector<int>& idx, const int* dims, const double* cells
   g.yg = 1;
   g.mid_kw = 4;
   g.mid_r = 0;
+  g.pbc = 0;
+  g.images = 0;
   if ((size_t)P * xrow_pitch_rt(g.lnx) * sizeof(float2) + 8192 > 160 * 1024)
     return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": coupled planes of one fine row must fit in 160 KiB of LDS");
   G.fx = fx;
@@ -729,14 +737,14 @@ const char* demag_last_error(void) { return g_err.c_str(); }
 
 int demag_setup(demag_plan** out, int nx, int ny, int nz, double dx, double dy, double dz, unsigned pbc_flags,
                 int pbc_images) {
-  (void)pbc_images;
   if (!out) return fail(DEMAG_EINVAL, "demag_setup: out is NULL");
   *out = nullptr;
   Geom g;
-  int rc = make_geom(nx, ny, nz, dx, dy, dz, g, "demag_setup");
-  if (rc != DEMAG_OK) return rc;
   if (pbc_flags & ~7u) return fail(DEMAG_EINVAL, "demag_setup: unknown boundary flags");
-  if (pbc_flags) return fail(DEMAG_EUNSUPPORTED, "demag_setup: periodic boundaries are not supported");
+  if (pbc_flags && pbc_images > MAX_IMAGES)
+    return fail(DEMAG_EINVAL, "demag_setup: at most 1000 images per side");
+  int rc = make_geom(nx, ny, nz, dx, dy, dz, pbc_flags, pbc_images, g, "demag_setup");
+  if (rc != DEMAG_OK) return rc;
   demag_plan* p = new (std::nothrow) demag_plan;
   if (!p) return fail(DEMAG_ENOMEM, "demag_setup: out of host memory");
   Sub sb;
@@ -752,12 +760,16 @@ int demag_setup(demag_plan** out, int nx, int ny, int nz, double dx, double dy, 
 
 int demag_setup_batch(demag_plan** out, int nmesh, const int* dims, const double* cells, const double* origins,
                       const int* groups, unsigned pbc_flags, int pbc_images) {
-  (void)pbc_images;
   if (!out) return fail(DEMAG_EINVAL, "demag_setup_batch: out is NULL");
   *out = nullptr;
   if (nmesh < 1 || !dims || !cells) return fail(DEMAG_EINVAL, "demag_setup_batch: need nmesh >= 1 and dims/cells");
   if (pbc_flags & ~7u) return fail(DEMAG_EINVAL, "demag_setup_batch: unknown boundary flags");
-  if (pbc_flags) return fail(DEMAG_EUNSUPPORTED, "demag_setup_batch: periodic boundaries are not supported");
+  if (pbc_flags && pbc_images > MAX_IMAGES)
+    return fail(DEMAG_EINVAL, "demag_setup_batch: at most 1000 images per side");
+  if (pbc_flags && groups)
+    for (int i = 0; i < nmesh; ++i)
+      if (groups[i] >= 0)
+        return fail(DEMAG_EUNSUPPORTED, "demag_setup_batch: periodic boundaries are not supported for coupled groups");
   demag_plan* p = new (std::nothrow) demag_plan;
   if (!p) return fail(DEMAG_ENOMEM, "demag_setup_batch: out of host memory");
   p->batch = true;
@@ -799,7 +811,7 @@ int demag_setup_batch(demag_plan** out, int nmesh, const int* dims, const double
     if (coupled[i]) continue;
     Geom g;
     const int rc = make_geom(dims[3 * i], dims[3 * i + 1], dims[3 * i + 2], cells[3 * i], cells[3 * i + 1],
-                             cells[3 * i + 2], g, "demag_setup_batch");
+                             cells[3 * i + 2], pbc_flags, pbc_images, g, "demag_setup_batch");
     if (rc != DEMAG_OK) {
       delete p;
       return rc;

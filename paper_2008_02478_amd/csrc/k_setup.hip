@@ -68,18 +68,12 @@ __device__ double stencil27(double X, double Y, double Z, double a, double b, do
   return acc / (4.0 * M_PI * a * b * c);
 }
 
-__global__ void k_tensor(double* __restrict__ out, int nx, int ny, int nz, double dx, double dy, double dz,
-                         GLTable gl) {
-  const size_t cnt = (size_t)nx * ny * nz;
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= cnt) return;
-  const int i = (int)(idx % nx);
-  const int j = (int)((idx / nx) % ny);
-  const int k = (int)(idx / ((size_t)nx * ny));
-  const double X = i * dx, Y = j * dy, Z = k * dz;
+// N at one offset (X, Y, Z): closed form within 3 h_max, Gauss-Legendre
+// quadrature of the tent-weighted dipole kernel beyond (order by distance).
+__device__ void tensor_point(double X, double Y, double Z, double dx, double dy, double dz, const GLTable& gl,
+                             double (&N)[6]) {
   const double hmax = fmax(dx, fmax(dy, dz));
   const double dist = sqrt(X * X + Y * Y + Z * Z) / hmax;
-  double N[6];
   if (dist < 3.0) {
     N[0] = stencil27<false>(X, Y, Z, dx, dy, dz);
     N[1] = stencil27<false>(Y, X, Z, dy, dx, dz);
@@ -87,37 +81,61 @@ __global__ void k_tensor(double* __restrict__ out, int nx, int ny, int nz, doubl
     N[3] = stencil27<true>(X, Y, Z, dx, dy, dz);
     N[4] = stencil27<true>(X, Z, Y, dx, dz, dy);
     N[5] = stencil27<true>(Y, Z, X, dy, dz, dx);
-  } else {
-    const int b = dist < 6.0 ? 0 : dist < 16.0 ? 1 : dist < 40.0 ? 2 : 3;
-    const int n = gl.n[b];
-    for (int q = 0; q < 6; ++q) N[q] = 0.0;
-    for (int ax = 0; ax < 2 * n; ++ax) {
-      const double ux = (ax < n ? 1.0 : -1.0) * gl.u[b][ax % n] * dx;
-      const double wx = gl.w[b][ax % n] * dx * (dx - fabs(ux));
-      const double vx = X + ux;
-      for (int ay = 0; ay < 2 * n; ++ay) {
-        const double uy = (ay < n ? 1.0 : -1.0) * gl.u[b][ay % n] * dy;
-        const double wy = gl.w[b][ay % n] * dy * (dy - fabs(uy));
-        const double vy = Y + uy;
-        for (int az = 0; az < 2 * n; ++az) {
-          const double uz = (az < n ? 1.0 : -1.0) * gl.u[b][az % n] * dz;
-          const double wz = gl.w[b][az % n] * dz * (dz - fabs(uz));
-          const double vz = Z + uz;
-          const double r2 = vx * vx + vy * vy + vz * vz;
-          const double wt = wx * wy * wz / (r2 * r2 * sqrt(r2));
-          N[0] += wt * (r2 - 3.0 * vx * vx);
-          N[1] += wt * (r2 - 3.0 * vy * vy);
-          N[2] += wt * (r2 - 3.0 * vz * vz);
-          N[3] -= wt * 3.0 * vx * vy;
-          N[4] -= wt * 3.0 * vx * vz;
-          N[5] -= wt * 3.0 * vy * vz;
-        }
+    return;
+  }
+  const int b = dist < 6.0 ? 0 : dist < 16.0 ? 1 : dist < 40.0 ? 2 : 3;
+  const int n = gl.n[b];
+  for (int q = 0; q < 6; ++q) N[q] = 0.0;
+  for (int ax = 0; ax < 2 * n; ++ax) {
+    const double ux = (ax < n ? 1.0 : -1.0) * gl.u[b][ax % n] * dx;
+    const double wx = gl.w[b][ax % n] * dx * (dx - fabs(ux));
+    const double vx = X + ux;
+    for (int ay = 0; ay < 2 * n; ++ay) {
+      const double uy = (ay < n ? 1.0 : -1.0) * gl.u[b][ay % n] * dy;
+      const double wy = gl.w[b][ay % n] * dy * (dy - fabs(uy));
+      const double vy = Y + uy;
+      for (int az = 0; az < 2 * n; ++az) {
+        const double uz = (az < n ? 1.0 : -1.0) * gl.u[b][az % n] * dz;
+        const double wz = gl.w[b][az % n] * dz * (dz - fabs(uz));
+        const double vz = Z + uz;
+        const double r2 = vx * vx + vy * vy + vz * vz;
+        const double wt = wx * wy * wz / (r2 * r2 * sqrt(r2));
+        N[0] += wt * (r2 - 3.0 * vx * vx);
+        N[1] += wt * (r2 - 3.0 * vy * vy);
+        N[2] += wt * (r2 - 3.0 * vz * vz);
+        N[3] -= wt * 3.0 * vx * vy;
+        N[4] -= wt * 3.0 * vx * vz;
+        N[5] -= wt * 3.0 * vy * vz;
       }
     }
-    const double s = 1.0 / (4.0 * M_PI * dx * dy * dz);
-    for (int q = 0; q < 6; ++q) N[q] *= s;
   }
-  for (int q = 0; q < 6; ++q) out[q * cnt + idx] = N[q];
+  const double s = 1.0 / (4.0 * M_PI * dx * dy * dz);
+  for (int q = 0; q < 6; ++q) N[q] *= s;
+}
+
+// Octant of the tensor, out[c][k][j][i] = N at (i dx, j dy, k dz).  Periodic
+// axes (multiple images, Sec. 3): the sum of N over the shifts
+// (kx Lx, ky Ly, kz Lz), |k_a| <= K_a, with L_a = n_a h_a and K_a = images on
+// a periodic axis, 0 otherwise.
+__global__ void k_tensor(double* __restrict__ out, int nx, int ny, int nz, double dx, double dy, double dz,
+                         GLTable gl, int Kx, int Ky, int Kz) {
+  const size_t cnt = (size_t)nx * ny * nz;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= cnt) return;
+  const int i = (int)(idx % nx);
+  const int j = (int)((idx / nx) % ny);
+  const int k = (int)(idx / ((size_t)nx * ny));
+  const double X = i * dx, Y = j * dy, Z = k * dz;
+  const double Lx = nx * dx, Ly = ny * dy, Lz = nz * dz;
+  double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int a = -Kx; a <= Kx; ++a)
+    for (int b = -Ky; b <= Ky; ++b)
+      for (int c = -Kz; c <= Kz; ++c) {
+        double N[6];
+        tensor_point(X + a * Lx, Y + b * Ly, Z + c * Lz, dx, dy, dz, gl, N);
+        for (int q = 0; q < 6; ++q) S[q] += N[q];
+      }
+  for (int q = 0; q < 6; ++q) out[q * cnt + idx] = S[q];
 }
 
 // out[c][o][k][q] = sum_i coef_i * in[c][o][i][q] * trig(i k), 0 <= k < nout,
@@ -340,8 +358,9 @@ namespace demag {
 
 hipError_t launch_tensor(double* out, const Geom& g, const GLTable& gl, hipStream_t s) {
   const size_t cnt = (size_t)g.nx * g.ny * g.nz;
+  const int K = g.images;
   hipLaunchKernelGGL(k_tensor, dim3((unsigned)((cnt + 127) / 128)), dim3(128), 0, s, out, g.nx, g.ny, g.nz, g.dx,
-                     g.dy, g.dz, gl);
+                     g.dy, g.dz, gl, (g.pbc & 1u) ? K : 0, (g.pbc & 2u) ? K : 0, (g.pbc & 4u) ? K : 0);
   return hipGetLastError();
 }
 

@@ -70,6 +70,8 @@ struct Geom {
   int yg;              // y rows per workgroup in the x passes
   int mid_kw;          // kx lines per workgroup of the middle pass (2, 4 or 8)
   int mid_r;           // points per lane of its y line FFT (0: line_radix)
+  unsigned pbc;        // periodic axes (bit 0 x, 1 y, 2 z): image-summed tensor
+  int images;          // images K on either side along each periodic axis
   double dx, dy, dz;
 };
 

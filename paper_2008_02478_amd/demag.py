@@ -55,7 +55,9 @@ class _Schedules:
 
 class DemagPlan(_Schedules):
     """Plan for one mesh of n = (nx, ny, nz) cells of size cell = (dx, dy, dz)
-    metres with open boundaries.  Builds the kernel spectrum on construction."""
+    metres.  pbc: OR of lib.PBC_X / PBC_Y / PBC_Z for periodic axes (multiple
+    images, `images` on either side; 0 = the library default).  Builds the
+    kernel spectrum on construction."""
 
     def __init__(self, n, cell, device=None, pbc=0, images=0):
         self._lib = _l.load()
@@ -159,7 +161,7 @@ class DemagBatch(_Schedules):
     `view(x, i)` returns mesh i's block.  Meshes of equal geometry share one
     kernel spectrum and run through the same launches."""
 
-    def __init__(self, meshes, device=None, origins=None, groups=None):
+    def __init__(self, meshes, device=None, origins=None, groups=None, pbc=0, images=0):
         self._lib = _l.load()
         self.meshes = [(tuple(int(v) for v in n), tuple(float(v) for v in h)) for n, h in meshes]
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -169,7 +171,7 @@ class DemagBatch(_Schedules):
         orig = (ctypes.c_double * (3 * k))(*[float(v) for o in origins for v in o]) if origins is not None else None
         grp = (ctypes.c_int * k)(*[int(v) for v in groups]) if groups is not None else None
         self._p = ctypes.c_void_p()
-        _l.check(self._lib.demag_setup_batch(ctypes.byref(self._p), k, dims, cells, orig, grp, 0, 0))
+        _l.check(self._lib.demag_setup_batch(ctypes.byref(self._p), k, dims, cells, orig, grp, int(pbc), int(images)))
         nm, tot = ctypes.c_int(), ctypes.c_size_t()
         offs = (ctypes.c_longlong * k)()
         _l.check(self._lib.demag_batch_layout(self._p, ctypes.byref(nm), offs, ctypes.byref(tot)))

@@ -45,7 +45,7 @@ def setup(lib, *args):
     ((4, 4, 4, 1e-9, float("nan"), 1e-9, 0, 0), L.EINVAL),
     ((4, 4, 4, 1e-9, 1e-9, float("inf"), 0, 0), L.EINVAL),
     ((4, 4, 4, 1e-9, 1e-9, 1e-9, 8, 0), L.EINVAL),
-    ((4, 4, 4, 1e-9, 1e-9, 1e-9, L.PBC_X, 3), L.EUNSUPPORTED),
+    ((4, 4, 4, 1e-9, 1e-9, 1e-9, L.PBC_X, 1001), L.EINVAL),
     ((4, 4, 17, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
     ((4, 1025, 4, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
     ((2049, 4, 4, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
@@ -273,3 +273,26 @@ def test_autotune_host_checks(lib, tmp_path):
         assert b"schedule cache" in lib.demag_last_error()
     assert n.value == 0
     lib.demag_destroy(p)
+
+
+@pytest.mark.parametrize("flags,images", [(L.PBC_X, 3), (L.PBC_Y, 0), (L.PBC_X | L.PBC_Y, -5),
+                                          (L.PBC_Z, 1000), (7, 2)])
+def test_periodic_setup_accepted(lib, flags, images):
+    rc, p = setup(lib, 20, 12, 2, 2e-9, 2e-9, 1e-9, flags, images)
+    assert rc == L.OK, lib.demag_last_error()
+    lib.demag_destroy(p)
+
+
+def test_periodic_batch_rules(lib):
+    k = 3
+    dims = (ctypes.c_int * (3 * k))(16, 16, 1, 16, 16, 1, 8, 8, 2)
+    cells = (ctypes.c_double * (3 * k))(*([1e-9] * (3 * k)))
+    orig = (ctypes.c_double * (3 * k))(0.0, 0.0, 0.0, 0.0, 0.0, 3e-9, 0.0, 0.0, 0.0)
+    p = ctypes.c_void_p()
+    grp = (ctypes.c_int * k)(0, 0, -1)
+    assert lib.demag_setup_batch(ctypes.byref(p), k, dims, cells, orig, grp, L.PBC_X, 4) == L.EUNSUPPORTED
+    assert not p.value
+    grp = (ctypes.c_int * k)(-1, -1, -1)
+    assert lib.demag_setup_batch(ctypes.byref(p), k, dims, cells, orig, grp, L.PBC_X | L.PBC_Y, 4) == L.OK
+    lib.demag_destroy(p)
+    assert lib.demag_setup_batch(ctypes.byref(p), k, dims, cells, orig, grp, 8, 4) == L.EINVAL
