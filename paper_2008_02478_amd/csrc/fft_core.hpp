@@ -51,26 +51,30 @@ __device__ __forceinline__ float2 twiddle(const float2* __restrict__ tw, int m, 
   return w;
 }
 
-// Compile-time cos(2 pi k / 32), 0 <= k <= 16, for the in-register butterflies.
-__device__ __forceinline__ constexpr float cos32(int k) {
-  return k == 0 ? 1.0f : k == 1 ? 0.98078528040323043f : k == 2 ? 0.92387953251128674f
-       : k == 3 ? 0.83146961230254524f : k == 4 ? 0.70710678118654752f : k == 5 ? 0.55557023301960218f
-       : k == 6 ? 0.38268343236508977f : k == 7 ? 0.19509032201612826f : k == 8 ? 0.0f
-       : -cos32(16 - k);
+// Compile-time cos(2 pi k / 64), 0 <= k <= 32, for the in-register
+// butterflies (values of the double-precision cosine, rounded to float).
+__device__ __forceinline__ constexpr float cos64(int k) {
+  return k == 0 ? 1.0f : k == 1 ? 0.9951847266721969f : k == 2 ? 0.9807852804032304f
+       : k == 3 ? 0.9569403357322088f : k == 4 ? 0.9238795325112867f : k == 5 ? 0.881921264348355f
+       : k == 6 ? 0.8314696123025452f : k == 7 ? 0.773010453362737f : k == 8 ? 0.7071067811865476f
+       : k == 9 ? 0.6343932841636455f : k == 10 ? 0.5555702330196023f : k == 11 ? 0.4713967368259978f
+       : k == 12 ? 0.38268343236508984f : k == 13 ? 0.29028467725446233f : k == 14 ? 0.19509032201612833f
+       : k == 15 ? 0.09801714032956077f : k == 16 ? 0.0f
+       : -cos64(32 - k);
 }
 
-// a * W_LEN^J (forward: exp(-2 pi i J/LEN); INV: conjugate), LEN <= 32, J < LEN/2.
+// a * W_LEN^J (forward: exp(-2 pi i J/LEN); INV: conjugate), LEN <= 64, J < LEN/2.
 template <int LEN, int J, bool INV>
 __device__ __forceinline__ float2 tw_const(float2 a) {
-  static_assert(LEN <= 32 && J < LEN / 2, "constant twiddle out of range");
-  constexpr int k = J * (32 / LEN);  // angle 2 pi k / 32, 0 <= k < 16
+  static_assert(LEN <= 64 && J < LEN / 2, "constant twiddle out of range");
+  constexpr int k = J * (64 / LEN);  // angle 2 pi k / 64, 0 <= k < 32
   if constexpr (k == 0) {
     return a;
-  } else if constexpr (k == 8) {     // -i (forward) / +i (inverse)
+  } else if constexpr (k == 16) {    // -i (forward) / +i (inverse)
     return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
   } else {
-    constexpr float c = cos32(k);
-    constexpr float s = cos32(k < 8 ? 8 - k : k - 8);  // sin(2 pi k/32) > 0
+    constexpr float c = cos64(k);
+    constexpr float s = cos64(k < 16 ? 16 - k : k - 16);  // sin(2 pi k/64) > 0
     // forward multiplies by (c - i s), inverse by (c + i s)
     if constexpr (INV) return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
     else return make_float2(a.x * c + a.y * s, a.y * c - a.x * s);
@@ -109,7 +113,7 @@ __device__ __forceinline__ void bfly_levels(float2 (&b)[R]) {
   }
 }
 
-// In-register DFT of R <= 16 points (radix-2 DIT, fully unrolled).
+// In-register DFT of R <= 64 points (radix-2 DIT, fully unrolled).
 template <int R, bool INV>
 __device__ __forceinline__ void dft(float2 (&a)[R]) {
   if constexpr (R == 1) {

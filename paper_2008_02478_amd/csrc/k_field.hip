@@ -35,7 +35,7 @@ __device__ __forceinline__ void zodd_twiddle(float2 (&v)[NZ / 2]) {
 // forward: x real-to-complex + z
 // ---------------------------------------------------------------------------
 template <int LNX, int LNZ>
-__global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_eu(LNX >= 12 ? 2 : 4, 8))) k_fwd_xz(FwdArgs a) {
+__global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_eu(LNX >= 12 || LNZ >= 6 ? 2 : 4, 8))) k_fwd_xz(FwdArgs a) {
   constexpr int NX = 1 << LNX;
   constexpr int NZ = 1 << LNZ;
   extern __shared__ float2 smem_base[];
@@ -401,7 +401,7 @@ k_mid(MidArgs a) {
 // inverse: z + x complex-to-real
 // ---------------------------------------------------------------------------
 template <int LNX, int LNZ>
-__global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_eu(LNX >= 12 ? 2 : 4, 8))) k_inv_zx(InvArgs a) {
+__global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_eu(LNX >= 12 || LNZ >= 6 ? 2 : 4, 8))) k_inv_zx(InvArgs a) {
   constexpr int NX = 1 << LNX;
   constexpr int NZ = 1 << LNZ;
   extern __shared__ float2 smem_base[];
@@ -566,6 +566,8 @@ static hipError_t inv_one(const Geom& g, const InvArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Nz = 64 (17 <= nz <= 32) only for Nx <= 1024: longer rows do not leave
+// room for 32 of them in LDS (the plan rejects those sizes first)
 #define DEMAG_Z_SWITCH(FN, LNX, ...)                      \
   switch (g.lnz) {                                        \
     case 0: return FN<LNX, 0>(__VA_ARGS__);               \
@@ -573,6 +575,9 @@ static hipError_t inv_one(const Geom& g, const InvArgs& a, hipStream_t s) {
     case 3: return FN<LNX, 3>(__VA_ARGS__);               \
     case 4: return FN<LNX, 4>(__VA_ARGS__);               \
     case 5: return FN<LNX, 5>(__VA_ARGS__);               \
+    case 6:                                               \
+      if constexpr (LNX <= 10) return FN<LNX, 6>(__VA_ARGS__); \
+      else return hipErrorInvalidValue;                   \
     default: return hipErrorInvalidValue;                 \
   }
 
