@@ -34,6 +34,7 @@ WORKLOADS = {
     "1024x1024x4": dict(n=(1024, 1024, 4), h=(2e-9, 2e-9, 1e-9), Ms=1.1e6, seed=11),
     "256x256x8": dict(n=(256, 256, 8), h=(4e-9, 4e-9, 4e-9), Ms=8e5, seed=2),
     "256x128x4": dict(n=(256, 128, 4), h=(5e-9, 5e-9, 2e-9), Ms=8e5, seed=4),
+    "256x256x64": dict(n=(256, 256, 64), h=(4e-9, 4e-9, 4e-9), Ms=8e5, seed=12),
 }
 
 

@@ -24,9 +24,10 @@
  *    plan share its work buffer and must be ordered on one stream.
  *  - Arrays of vectors are SoA [3][nz][ny][nx], x fastest, FP32.  Lengths in
  *    metres, M and H in A/m, energies in joules (FP64).
- *  - Supported sizes: 1 <= nx <= 2048, 1 <= ny <= 1024, 1 <= nz <= 32 (nz > 16
- *    only with nx <= 512); each axis zero-padded to the next power of two
- *    >= 2n-1.  The z rows of one y line must also fit in 160 KiB of LDS.
+ *  - Supported sizes: 1 <= nx <= 2048, 1 <= ny <= 1024, 1 <= nz <= 64 (nz > 16
+ *    only with nx <= 512, nz > 32 only with nx <= 256); each axis zero-padded
+ *    to the next power of two >= 2n-1.  The z rows of one y line must also fit
+ *    in 160 KiB of LDS.
  *  - Periodic boundaries (Sec. 3, multiple images): along a periodic axis a
  *    (period L_a = n_a h_a) the mesh is repeated pbc_images times on either
  *    side and the field is that of the repeated mesh in its central copy,

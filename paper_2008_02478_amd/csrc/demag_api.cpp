@@ -144,10 +144,10 @@ int make_geom(int nx, int ny, int nz, double dx, double dy, double dz, unsigned 
   if (nx < 1 || ny < 1 || nz < 1) return fail(DEMAG_EINVAL, std::string(who) + ": mesh dimensions must be >= 1");
   if (!(std::isfinite(dx) && std::isfinite(dy) && std::isfinite(dz)) || dx <= 0 || dy <= 0 || dz <= 0)
     return fail(DEMAG_EINVAL, std::string(who) + ": cell sizes must be finite and > 0");
-  if (nx > 2048 || ny > 1024 || nz > 32)
-    return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": supported sizes are nx <= 2048, ny <= 1024, nz <= 32");
-  if (nz > 16 && nx > 512)
-    return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": nz > 16 needs nx <= 512");
+  if (nx > 2048 || ny > 1024 || nz > 64)
+    return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": supported sizes are nx <= 2048, ny <= 1024, nz <= 64");
+  if ((nz > 16 && nx > 512) || (nz > 32 && nx > 256))
+    return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": nz > 16 needs nx <= 512, nz > 32 needs nx <= 256");
   g = Geom{};
   g.nx = nx; g.ny = ny; g.nz = nz;
   g.Nx = padded(nx); g.Ny = padded(ny); g.Nz = padded(nz);

@@ -51,30 +51,35 @@ __device__ __forceinline__ float2 twiddle(const float2* __restrict__ tw, int m, 
   return w;
 }
 
-// Compile-time cos(2 pi k / 64), 0 <= k <= 32, for the in-register
+// Compile-time cos(2 pi k / 128), 0 <= k <= 64, for the in-register
 // butterflies (values of the double-precision cosine, rounded to float).
-__device__ __forceinline__ constexpr float cos64(int k) {
-  return k == 0 ? 1.0f : k == 1 ? 0.9951847266721969f : k == 2 ? 0.9807852804032304f
-       : k == 3 ? 0.9569403357322088f : k == 4 ? 0.9238795325112867f : k == 5 ? 0.881921264348355f
-       : k == 6 ? 0.8314696123025452f : k == 7 ? 0.773010453362737f : k == 8 ? 0.7071067811865476f
-       : k == 9 ? 0.6343932841636455f : k == 10 ? 0.5555702330196023f : k == 11 ? 0.4713967368259978f
-       : k == 12 ? 0.38268343236508984f : k == 13 ? 0.29028467725446233f : k == 14 ? 0.19509032201612833f
-       : k == 15 ? 0.09801714032956077f : k == 16 ? 0.0f
-       : -cos64(32 - k);
+__device__ __forceinline__ constexpr float cos128(int k) {
+  return k == 0 ? 1.0f : k == 1 ? 0.9987954562051724f : k == 2 ? 0.9951847266721969f :
+       k == 3 ? 0.989176509964781f : k == 4 ? 0.9807852804032304f : k == 5 ? 0.970031253194544f :
+       k == 6 ? 0.9569403357322088f : k == 7 ? 0.9415440651830208f : k == 8 ? 0.9238795325112867f :
+       k == 9 ? 0.9039892931234433f : k == 10 ? 0.881921264348355f : k == 11 ? 0.8577286100002721f :
+       k == 12 ? 0.8314696123025452f : k == 13 ? 0.8032075314806449f : k == 14 ? 0.773010453362737f :
+       k == 15 ? 0.7409511253549591f : k == 16 ? 0.7071067811865476f : k == 17 ? 0.6715589548470183f :
+       k == 18 ? 0.6343932841636455f : k == 19 ? 0.5956993044924335f : k == 20 ? 0.5555702330196023f :
+       k == 21 ? 0.5141027441932217f : k == 22 ? 0.4713967368259978f : k == 23 ? 0.4275550934302822f :
+       k == 24 ? 0.38268343236508984f : k == 25 ? 0.33688985339222005f : k == 26 ? 0.29028467725446233f :
+       k == 27 ? 0.24298017990326398f : k == 28 ? 0.19509032201612833f : k == 29 ? 0.14673047445536175f :
+       k == 30 ? 0.09801714032956077f : k == 31 ? 0.049067674327418126f : k == 32 ? 0.0f
+       : -cos128(64 - k);
 }
 
-// a * W_LEN^J (forward: exp(-2 pi i J/LEN); INV: conjugate), LEN <= 64, J < LEN/2.
+// a * W_LEN^J (forward: exp(-2 pi i J/LEN); INV: conjugate), LEN <= 128, J < LEN/2.
 template <int LEN, int J, bool INV>
 __device__ __forceinline__ float2 tw_const(float2 a) {
-  static_assert(LEN <= 64 && J < LEN / 2, "constant twiddle out of range");
-  constexpr int k = J * (64 / LEN);  // angle 2 pi k / 64, 0 <= k < 32
+  static_assert(LEN <= 128 && J < LEN / 2, "constant twiddle out of range");
+  constexpr int k = J * (128 / LEN);  // angle 2 pi k / 128, 0 <= k < 64
   if constexpr (k == 0) {
     return a;
-  } else if constexpr (k == 16) {    // -i (forward) / +i (inverse)
+  } else if constexpr (k == 32) {    // -i (forward) / +i (inverse)
     return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
   } else {
-    constexpr float c = cos64(k);
-    constexpr float s = cos64(k < 16 ? 16 - k : k - 16);  // sin(2 pi k/64) > 0
+    constexpr float c = cos128(k);
+    constexpr float s = cos128(k < 32 ? 32 - k : k - 32);  // sin(2 pi k/128) > 0
     // forward multiplies by (c - i s), inverse by (c + i s)
     if constexpr (INV) return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
     else return make_float2(a.x * c + a.y * s, a.y * c - a.x * s);
@@ -113,7 +118,7 @@ __device__ __forceinline__ void bfly_levels(float2 (&b)[R]) {
   }
 }
 
-// In-register DFT of R <= 64 points (radix-2 DIT, fully unrolled).
+// In-register DFT of R <= 128 points (radix-2 DIT, fully unrolled).
 template <int R, bool INV>
 __device__ __forceinline__ void dft(float2 (&a)[R]) {
   if constexpr (R == 1) {

@@ -95,6 +95,23 @@ __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_e
       Tc[o] = smem[(yl * nz) * PITCH + kx];
     } else {
       constexpr int Q = NZ / 2;
+      if constexpr (NZ >= 128) {
+        // long z lines: one residue in registers at a time, the column read
+        // from LDS once per residue
+        const float2* const col = smem + (yl * nz) * PITCH + kx;
+        float2 v[Q];
+#pragma unroll
+        for (int z = 0; z < Q; ++z) v[z] = (z < nz) ? col[z * PITCH] : make_float2(0.f, 0.f);
+        dft<Q, false>(v);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) Tc[o + (unsigned)(2 * k) * kzstride] = v[k];
+#pragma unroll
+        for (int z = 0; z < Q; ++z) v[z] = (z < nz) ? col[z * PITCH] : make_float2(0.f, 0.f);
+        zodd_twiddle<NZ, 0, false>(v);
+        dft<Q, false>(v);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) Tc[o + (unsigned)(2 * k + 1) * kzstride] = v[k];
+      } else {
       float2 xz[Q];
 #pragma unroll
       for (int z = 0; z < Q; ++z)
@@ -109,6 +126,7 @@ __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_e
       dft<Q, false>(xz);
 #pragma unroll
       for (int k = 0; k < Q; ++k) Tc[o + (unsigned)(2 * k + 1) * kzstride] = xz[k];
+      }
     }
   }
 }
@@ -441,18 +459,36 @@ __global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_e
       d0[0] = Tc[o];
     } else {
       constexpr int Q = NZ / 2;
-      // both residues requested before either is transformed
-      float2 v[Q], w[Q];
+      // both residues requested before either is transformed (one at a time
+      // for the longest lines, whose two residues would not fit in registers)
+      constexpr int QW = NZ >= 128 ? 1 : Q;
+      float2 v[Q], w[QW];
+      // residue loads of the longest lines go in chunks of 16, so that few
+      // addresses are live at once
+      auto load_res = [&](int par) __attribute__((always_inline)) {
+        constexpr int CH = Q > 16 ? 16 : Q;
 #pragma unroll
-      for (int k = 0; k < Q; ++k) v[k] = Tc[o + (unsigned)(2 * k) * kzstride];
+        for (int k0 = 0; k0 < Q; k0 += CH) {
 #pragma unroll
-      for (int k = 0; k < Q; ++k) w[k] = Tc[o + (unsigned)(2 * k + 1) * kzstride];
+          for (int k = k0; k < k0 + CH; ++k) v[k] = Tc[o + (unsigned)(2 * k + par) * kzstride];
+          if constexpr (NZ >= 128) asm volatile("" ::: "memory");
+        }
+      };
+      load_res(0);
+      if constexpr (NZ < 128) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) w[k] = Tc[o + (unsigned)(2 * k + 1) * kzstride];
+      }
       dft<Q, true>(v);
 #pragma unroll
       for (int z = 0; z < Q; ++z)
         if (z < nz) d0[z * PITCH] = v[z];
+      if constexpr (NZ < 128) {
 #pragma unroll
-      for (int k = 0; k < Q; ++k) v[k] = w[k];
+        for (int k = 0; k < Q; ++k) v[k] = w[k];
+      } else {
+        load_res(1);
+      }
       dft<Q, true>(v);
       zodd_twiddle<NZ, 0, true>(v);
 #pragma unroll
@@ -566,8 +602,9 @@ static hipError_t inv_one(const Geom& g, const InvArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Nz = 64 (17 <= nz <= 32) only for Nx <= 1024: longer rows do not leave
-// room for 32 of them in LDS (the plan rejects those sizes first)
+// Nz = 64 (17 <= nz <= 32) only for Nx <= 1024 and Nz = 128 (33 <= nz <= 64)
+// only for Nx <= 512: longer rows do not leave room for that many of them in
+// LDS (the plan rejects those sizes first)
 #define DEMAG_Z_SWITCH(FN, LNX, ...)                      \
   switch (g.lnz) {                                        \
     case 0: return FN<LNX, 0>(__VA_ARGS__);               \
@@ -577,6 +614,9 @@ static hipError_t inv_one(const Geom& g, const InvArgs& a, hipStream_t s) {
     case 5: return FN<LNX, 5>(__VA_ARGS__);               \
     case 6:                                               \
       if constexpr (LNX <= 10) return FN<LNX, 6>(__VA_ARGS__); \
+      else return hipErrorInvalidValue;                   \
+    case 7:                                               \
+      if constexpr (LNX <= 9) return FN<LNX, 7>(__VA_ARGS__); \
       else return hipErrorInvalidValue;                   \
     default: return hipErrorInvalidValue;                 \
   }

@@ -46,7 +46,8 @@ def setup(lib, *args):
     ((4, 4, 4, 1e-9, 1e-9, float("inf"), 0, 0), L.EINVAL),
     ((4, 4, 4, 1e-9, 1e-9, 1e-9, 8, 0), L.EINVAL),
     ((4, 4, 4, 1e-9, 1e-9, 1e-9, L.PBC_X, 1001), L.EINVAL),
-    ((4, 4, 33, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
+    ((4, 4, 65, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
+    ((300, 4, 33, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
     ((600, 4, 17, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
     ((4, 1025, 4, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
     ((2049, 4, 4, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
@@ -144,7 +145,7 @@ def test_batch_setup_and_layout(lib):
 
 @pytest.mark.parametrize("n,code", [(0, L.EINVAL), (2, L.EUNSUPPORTED)])
 def test_batch_setup_rejects(lib, n, code):
-    dims = (ctypes.c_int * 6)(4, 3, 2, 4, 3, 33)
+    dims = (ctypes.c_int * 6)(4, 3, 2, 4, 3, 65)
     cells = (ctypes.c_double * 6)(1e-9, 1e-9, 1e-9, 1e-9, 1e-9, 1e-9)
     p = ctypes.c_void_p()
     assert lib.demag_setup_batch(ctypes.byref(p), n, dims, cells, None, None, 0, 0) == code

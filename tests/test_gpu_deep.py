@@ -1,4 +1,5 @@
-"""GPU parity for meshes with more than 16 cells along z (padded z length 64):
+"""GPU parity for meshes with more than 16 cells along z (padded z length 64
+or 128):
 the z transforms stay fused with the x transforms while the z rows of a y
 line fit in LDS (Sec. 7; the pipelined form of the paper applies up to 16
 cells, longer lines are the general 3D case).  Field, energy and backward
@@ -24,6 +25,8 @@ def torch():
     ((64, 48, 32), (4e-9, 4e-9, 4e-9)),
     ((1, 1, 32), (5e-9, 5e-9, 3e-9)),
     ((256, 256, 32), (4e-9, 4e-9, 4e-9)),
+    ((40, 24, 33), (3e-9, 3e-9, 2e-9)),
+    ((256, 256, 64), (4e-9, 4e-9, 4e-9)),
 ])
 def test_deep_meshes(torch, n, h):
     from paper_2008_02478_amd.demag import DemagPlan
@@ -36,7 +39,7 @@ def test_deep_meshes(torch, n, h):
     Er = conv.energy(M, Hr, h)
     gr = Ms * conv.fft_conv(G.astype(np.float64), h)
     plan = DemagPlan(n, h)
-    assert plan.padded[2] == 64
+    assert plan.padded[2] == (64 if n[2] <= 32 else 128)
     H, E = plan.field(to_dev(m, torch), Ms, energy=True)
     g = plan.backward(to_dev(G, torch), Ms)
     torch.cuda.synchronize()
