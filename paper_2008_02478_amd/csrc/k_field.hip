@@ -205,7 +205,11 @@ k_mid(MidArgs a) {
     if (ENERGY && tid == 0) a.epart[lg] = 0.0;
     return;
   }
-  float2* stage = smem;                     // 3 components x ny * KW points
+  // staging of the three components' blocks: rows of KWP = KW + 1 points per
+  // y (an odd pitch, so the lanes of a job, which read consecutive y, hit
+  // distinct LDS banks)
+  constexpr int KWP = KW + 1;
+  float2* stage = smem;                     // 3 components x ny * KWP points
   float2* scr = smem + (size_t)job * lds_points<M, R>();   // per-job scratch (aliases stage)
   const size_t cstride = (size_t)a.Nz * a.nTiles * ny * TILE;
   float2* blk0 = a.T + ((size_t)kz * a.nTiles + tile) * ny * TILE + half * KW;
@@ -275,11 +279,15 @@ k_mid(MidArgs a) {
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      float4* st4 = reinterpret_cast<float4*>(stage + c * ny * KW);
 #pragma unroll
       for (int i = 0; i < ITER; ++i) {
         const int e = tid + i * NTH;
-        if (e < nv) st4[e] = pre[c][i];
+        if (e < nv) {
+          const int y = e / V, q = e - y * V;
+          float2* const d = stage + c * ny * KWP + y * KWP + 2 * q;
+          d[0] = make_float2(pre[c][i].x, pre[c][i].y);
+          d[1] = make_float2(pre[c][i].z, pre[c][i].w);
+        }
       }
     }
     __syncthreads();
@@ -288,7 +296,7 @@ k_mid(MidArgs a) {
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         const int y = t + T * j;
-        v[c][j] = (valid && y < ny) ? stage[c * ny * KW + y * KW + w] : make_float2(0.f, 0.f);
+        v[c][j] = (valid && y < ny) ? stage[c * ny * KWP + y * KWP + w] : make_float2(0.f, 0.f);
       }
       if constexpr (NRES == 2) residue_twiddle<R, false>(v[c], rbase, r != 0);
     }
@@ -381,7 +389,7 @@ k_mid(MidArgs a) {
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         const int y = t + T * j;
-        if (y < ny) stage[c * ny * KW + y * KW + w] = v[c][j];
+        if (y < ny) stage[c * ny * KWP + y * KWP + w] = v[c][j];
       }
   }
   __syncthreads();
@@ -392,7 +400,7 @@ k_mid(MidArgs a) {
 #pragma unroll
         for (int j = 0; j < R; ++j) {
           const int y = t + T * j;
-          if (y < ny) stage[c * ny * KW + y * KW + w] = cadd(stage[c * ny * KW + y * KW + w], v[c][j]);
+          if (y < ny) stage[c * ny * KWP + y * KWP + w] = cadd(stage[c * ny * KWP + y * KWP + w], v[c][j]);
         }
     }
     __syncthreads();
@@ -401,11 +409,12 @@ k_mid(MidArgs a) {
     constexpr int V = KW / 2;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const float4* st4 = reinterpret_cast<const float4*>(stage + c * ny * KW);
       float4* b4 = reinterpret_cast<float4*>(blk0 + c * cstride);
       for (int q = tid; q < ny * V; q += blockDim.x) {
         const int y = q / V, s2 = q - y * V;
-        b4[(unsigned)y * (TILE / 2) + s2] = st4[q];
+        const float2* const src = stage + c * ny * KWP + y * KWP + 2 * s2;
+        const float2 lo = src[0], hi = src[1];
+        b4[(unsigned)y * (TILE / 2) + s2] = make_float4(lo.x, lo.y, hi.x, hi.y);
       }
     }
   }
@@ -665,7 +674,7 @@ static hipError_t mid_launch(const Geom& g, const MidArgs& a, hipStream_t s) {
   constexpr int M = NY > 1 ? NY / 2 : 1;
   constexpr int NRES = NY > 1 ? 2 : 1;
   size_t lds = (size_t)NRES * KW * lds_points<M, R>() * sizeof(float2);
-  const size_t st = (size_t)3 * g.ny * KW * sizeof(float2);   // staging of the three components
+  const size_t st = (size_t)3 * g.ny * (KW + 1) * sizeof(float2);   // staging of the three components
   if (st > lds) lds = st;
   const size_t klp = NRES == 2 ? kernel_row_pitch(NY) + 4 : kernel_row_pitch(NY);
   const size_t kr = MODE == 0 ? (size_t)KW * 6 * klp * sizeof(float) : 0;   // kernel rows
