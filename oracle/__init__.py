@@ -15,6 +15,9 @@ Contents
              over a collection of meshes (Sec. 3).
   pbc.py     image-summed tensor for periodic boundaries (Sec. 3, multiple
              images).
+  llg.py     a minimal evaluation loop: exchange and applied fields, the LLG
+             equation (Sec. 2, Eq. 1), RK4 steps (Sec. 7), the two-sublattice
+             demagnetizing input (Sec. 6).
 """
 from .newell import (COMPONENTS, newell_f, newell_g, newell_near, gl_far,
                      tensor_at, tensor_octant, tensor_full)
