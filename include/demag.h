@@ -155,6 +155,42 @@ int demag_backward_batch(const demag_plan* plan, const float* d_G, const float* 
  * NULL (or count 0) turns recording off.  Host-only bookkeeping. */
 int demag_set_timing_events(demag_plan* plan, void* const* events, int count);
 
+/* Demagnetizing field of two sublattices (Sec. 6): the field of the mean
+ * magnetization (MsA mA + MsB mB) / 2, with d_mA, d_mB unit-vector fields of
+ * the plan's mesh and scalar saturation magnetizations.  d_energy, when
+ * given, receives -(mu0/2) V sum M . H_d of that mean M.  Single-mesh plans;
+ * otherwise as demag_field. */
+int demag_field_2sub(const demag_plan* plan, const float* d_mA, const float* d_mB, float MsA, float MsB,
+                     float* d_H, unsigned flags, double* d_energy, void* stream);
+
+/* A minimal evaluation loop around the demagnetizing field: one classical
+ * RK4 step of the LLG equation (Sec. 2, Eq. 1, in its explicit form
+ * dm/dt = -gamma/(1 + alpha^2) [m x H + alpha m x (m x H)]), with
+ * H = demagnetizing + applied + direct exchange (Appendix A, Table 1:
+ * (2A / (mu0 Ms)) lap(m), discrete Neumann condition, periodic along the
+ * plan's periodic axes).  Four field evaluations per step (Sec. 7's
+ * benchmark counts time per evaluation); m is renormalized after the step.
+ *   Ms     saturation magnetization (A/m), > 0
+ *   A      exchange stiffness (J/m), >= 0
+ *   alpha  Gilbert damping, >= 0
+ *   gamma  mu0 g_rel |gamma_e| in m/(A s); <= 0 selects mu0 * 1.76085963023e11
+ *   dt     time step (s), > 0
+ *   Hext   applied field (A/m) */
+typedef struct {
+  float Ms, A, alpha, gamma, dt;
+  float Hext[3];
+} demag_llg_params;
+
+/* Device workspace of demag_llg_rk4 (4 vectors of the mesh, 256-byte aligned
+ * slices).  Single-mesh plans. */
+int demag_llg_workspace_bytes(const demag_plan* plan, size_t* bytes);
+
+/* One RK4 step in place on d_m (unit vectors, SoA) on `stream`; d_work as
+ * sized by demag_llg_workspace_bytes (caller-owned, 256-byte aligned).  Only
+ * enqueues work (graph-capturable).  DEMAG_EINVAL for NULL or non-finite
+ * parameters, Ms <= 0, dt <= 0, A < 0 or alpha < 0; single-mesh plans. */
+int demag_llg_rk4(const demag_plan* plan, float* d_m, const demag_llg_params* params, void* d_work, void* stream);
+
 /* Launch schedules.  Each plan has parts: one per group of identical
  * independent meshes (a single-mesh plan has one), then one per coupled
  * group.  A part's schedule is its launch shape:

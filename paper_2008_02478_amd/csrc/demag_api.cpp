@@ -462,10 +462,11 @@ int mark(const demag_plan* p, int i, hipStream_t s) {
 }
 
 FwdArgs fwd_args(const demag_plan* p, const Sub& sb, const float* src, const float* Ms, float ms,
-                 const float* ms_mesh) {
+                 const float* ms_mesh, const float* src2 = nullptr, float ms2 = 0.f) {
   const Geom& g = sb.g;
   return FwdArgs{src, Ms, ms, sb.T, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, (int)sb.members.size(),
-                 p->batch ? sb.moff : nullptr, ms_mesh, spectrum_elems(g), p->batch ? sb.gid : nullptr};
+                 p->batch ? sb.moff : nullptr, ms_mesh, spectrum_elems(g), p->batch ? sb.gid : nullptr,
+                 src2, ms2};
 }
 
 MidArgs mid_args(const demag_plan* p, const Sub& sb, bool energy) {
@@ -474,13 +475,13 @@ MidArgs mid_args(const demag_plan* p, const Sub& sb, bool energy) {
                  TILE / mid_kw(g), (int)sb.members.size(), spectrum_elems(g), mid_blocks(g)};
 }
 
-// forward and middle passes of one sub-plan
+// forward and middle passes of one sub-plan (src2: optional second sublattice)
 int run_conv(const demag_plan* p, const Sub& sb, const float* src, const float* Ms, float ms,
-             const float* ms_mesh, bool energy, hipStream_t s) {
+             const float* ms_mesh, bool energy, hipStream_t s, const float* src2 = nullptr, float ms2 = 0.f) {
   const Geom& g = sb.g;
   int rc = mark(p, 0, s);
   if (rc != DEMAG_OK) return rc;
-  hipError_t e = launch_fwd(g, fwd_args(p, sb, src, Ms, ms, ms_mesh), s);
+  hipError_t e = launch_fwd(g, fwd_args(p, sb, src, Ms, ms, ms_mesh, src2, ms2), s);
   if (e != hipSuccess) return fail_hip(e, "forward pass");
   if ((rc = mark(p, 1, s)) != DEMAG_OK) return rc;
   e = launch_mid(g, mid_args(p, sb, energy), s);
@@ -489,11 +490,11 @@ int run_conv(const demag_plan* p, const Sub& sb, const float* src, const float* 
 }
 
 int run_field(const demag_plan* p, const float* d_m, const float* d_Ms, float Ms, const float* ms_mesh, float* d_H,
-              unsigned flags, double* d_energy, hipStream_t s) {
+              unsigned flags, double* d_energy, hipStream_t s, const float* d_m2 = nullptr, float Ms2 = 0.f) {
   for (const Sub& sb : p->subs) {
     const Geom& g = sb.g;
     const int nb = (int)sb.members.size();
-    int rc = run_conv(p, sb, d_m, d_Ms, Ms, ms_mesh, d_energy != nullptr, s);
+    int rc = run_conv(p, sb, d_m, d_Ms, Ms, ms_mesh, d_energy != nullptr, s, d_m2, Ms2);
     if (rc != DEMAG_OK) return rc;
     InvArgs ia{sb.T, d_H, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, (flags & DEMAG_ACCUMULATE) ? 1 : 0,
                nullptr, nullptr, 0.0, nullptr, 0.f, 0,
@@ -924,6 +925,18 @@ int demag_field(const demag_plan* p, const float* d_m, const float* d_Ms, float 
   return run_field(p, d_m, d_Ms, Ms, nullptr, d_H, flags, d_energy, static_cast<hipStream_t>(stream));
 }
 
+int demag_field_2sub(const demag_plan* p, const float* d_mA, const float* d_mB, float MsA, float MsB, float* d_H,
+                     unsigned flags, double* d_energy, void* stream) {
+  if (!p) return fail(DEMAG_EINVAL, "demag_field_2sub: plan is NULL");
+  if (p->batch) return fail(DEMAG_EINVAL, "demag_field_2sub: single-mesh plans only");
+  if (!p->bound) return fail(DEMAG_ESTATE, "demag_field_2sub: plan is not bound");
+  if (!d_mA || !d_mB || !d_H) return fail(DEMAG_EINVAL, "demag_field_2sub: NULL mA, mB or H");
+  if (flags & ~(unsigned)DEMAG_ACCUMULATE) return fail(DEMAG_EINVAL, "demag_field_2sub: unknown flags");
+  if (!std::isfinite(MsA) || !std::isfinite(MsB)) return fail(DEMAG_EINVAL, "demag_field_2sub: Ms is not finite");
+  return run_field(p, d_mA, nullptr, MsA, nullptr, d_H, flags, d_energy, static_cast<hipStream_t>(stream), d_mB,
+                   MsB);
+}
+
 int demag_field_batch(const demag_plan* p, const float* d_m, const float* d_Ms_mesh, float Ms, float* d_H,
                       unsigned flags, double* d_energy, void* stream) {
   if (!p) return fail(DEMAG_EINVAL, "demag_field_batch: plan is NULL");
@@ -1072,6 +1085,65 @@ int demag_autotune(demag_plan* p, const float* d_m, float* d_H, const char* cach
   if (measured) *measured = nmeas;
   if (cache_path && nmeas > 0 && !tune_cache_write(cache_path, cache, err))
     return fail(DEMAG_EINVAL, "demag_autotune: " + err);
+  return DEMAG_OK;
+}
+
+int demag_llg_workspace_bytes(const demag_plan* p, size_t* bytes) {
+  if (!p || !bytes) return fail(DEMAG_EINVAL, "demag_llg_workspace_bytes: NULL argument");
+  if (p->batch) return fail(DEMAG_EINVAL, "demag_llg_workspace_bytes: single-mesh plans only");
+  const Geom& g = p->subs[0].g;
+  *bytes = 4 * align256((size_t)3 * g.nx * g.ny * g.nz * sizeof(float));
+  return DEMAG_OK;
+}
+
+int demag_llg_rk4(const demag_plan* p, float* d_m, const demag_llg_params* prm, void* d_work, void* stream) {
+  if (!p || !d_m || !prm || !d_work) return fail(DEMAG_EINVAL, "demag_llg_rk4: NULL argument");
+  if (p->batch) return fail(DEMAG_EINVAL, "demag_llg_rk4: single-mesh plans only");
+  if (!p->bound) return fail(DEMAG_ESTATE, "demag_llg_rk4: plan is not bound");
+  if (!aligned(d_work)) return fail(DEMAG_EINVAL, "demag_llg_rk4: workspace must be 256-byte aligned");
+  const float vals[8] = {prm->Ms, prm->A, prm->alpha, prm->gamma, prm->dt, prm->Hext[0], prm->Hext[1], prm->Hext[2]};
+  for (float v : vals)
+    if (!std::isfinite(v)) return fail(DEMAG_EINVAL, "demag_llg_rk4: parameters must be finite");
+  if (!(prm->Ms > 0.f) || !(prm->dt > 0.f) || prm->A < 0.f || prm->alpha < 0.f)
+    return fail(DEMAG_EINVAL, "demag_llg_rk4: need Ms > 0, dt > 0, A >= 0, alpha >= 0");
+  const Geom& g = p->subs[0].g;
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  const size_t vb = align256(3 * n * sizeof(float));
+  char* w = static_cast<char*>(d_work);
+  float* sA = reinterpret_cast<float*>(w);
+  float* sB = reinterpret_cast<float*>(w + vb);
+  float* acc = reinterpret_cast<float*>(w + 2 * vb);
+  float* H = reinterpret_cast<float*>(w + 3 * vb);
+  const double gamma = prm->gamma > 0.f ? (double)prm->gamma : MU0 * 1.76085963023e11;
+  const double alpha = prm->alpha;
+  LlgArgs la{};
+  la.m0 = d_m;
+  la.acc = acc;
+  la.nx = g.nx; la.ny = g.ny; la.nz = g.nz;
+  la.pbc = g.pbc;
+  la.ihx2 = (float)(1.0 / (g.dx * g.dx));
+  la.ihy2 = (float)(1.0 / (g.dy * g.dy));
+  la.ihz2 = (float)(1.0 / (g.dz * g.dz));
+  la.cex = (float)(2.0 * prm->A / (MU0 * prm->Ms));
+  la.hx = prm->Hext[0]; la.hy = prm->Hext[1]; la.hz = prm->Hext[2];
+  la.gp = (float)(gamma / (1.0 + alpha * alpha));
+  la.alpha = prm->alpha;
+  la.dt = prm->dt;
+  la.Hd = H;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // stage inputs: m, sA, sB, sA; stage 3 writes the new state over m
+  const float* in[4] = {d_m, sA, sB, sA};
+  float* nxt[3] = {sA, sB, sA};
+  for (int st = 0; st < 4; ++st) {
+    int rc = run_field(p, in[st], nullptr, prm->Ms, nullptr, H, 0u, nullptr, s);
+    if (rc != DEMAG_OK) return rc;
+    la.mi = in[st];
+    la.stage = st;
+    la.next = st < 3 ? nxt[st] : nullptr;
+    la.mout = st == 3 ? d_m : nullptr;
+    const hipError_t e = launch_llg_stage(la, s);
+    if (e != hipSuccess) return fail_hip(e, "LLG stage");
+  }
   return DEMAG_OK;
 }
 

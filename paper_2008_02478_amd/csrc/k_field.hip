@@ -62,7 +62,9 @@ __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_e
       const int yl = row / nz, z = row - yl * nz;
       const size_t off = ((size_t)z * ny + (y0 + yl)) * nx;
       const float ms = a.Ms ? a.Ms[off] : a.ms;
-      smem[row * PITCH] = make_float2(a.m[(size_t)c * nz * ny * nx + off] * ms, 0.f);
+      float v = a.m[(size_t)c * nz * ny * nx + off] * ms;
+      if (a.m2) v = 0.5f * (v + a.ms2 * a.m2[(size_t)c * nz * ny * nx + off]);
+      smem[row * PITCH] = make_float2(v, 0.f);
     }
   } else {
     const bool even = (nx & 1) == 0;
@@ -74,6 +76,14 @@ __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_e
       if (even) return xi < nx ? reinterpret_cast<const float2*>(src)[mm] : make_float2(0.f, 0.f);
       return make_float2(xi < nx ? src[xi] : 0.f, xi + 1 < nx ? src[xi + 1] : 0.f);
     }, [&](int row, int mm, float2 v) -> float2 {
+      if (a.m2) {
+        // two sublattices: (ms m + ms2 m2) / 2, the second read here
+        const int yl = row / nz, z = row - yl * nz;
+        const float* src2 = a.m2 + (size_t)c * nz * ny * nx + ((size_t)z * ny + (y0 + yl)) * nx;
+        const int xi = 2 * mm;
+        const float w0 = xi < nx ? src2[xi] : 0.f, w1 = xi + 1 < nx ? src2[xi + 1] : 0.f;
+        return make_float2(0.5f * (a.ms * v.x + a.ms2 * w0), 0.5f * (a.ms * v.y + a.ms2 * w1));
+      }
       if (!a.Ms) return make_float2(v.x * a.ms, v.y * a.ms);
       const int yl = row / nz, z = row - yl * nz;
       const float* msr = a.Ms + ((size_t)z * ny + (y0 + yl)) * nx;

@@ -32,5 +32,6 @@ hipError_t launch_pair_tensor(double2* out, const PairGeom& pg, const GLTable& g
 hipError_t launch_fft64(double2* data, int logN, long long es, long long ls, int lpb, long long bstride, int nlines,
                         const double2* tw64, hipStream_t s);
 hipError_t launch_pair_pack(const double2* in, float2* K, int Nx, int Ny, int Kx, double scale, hipStream_t s);
+hipError_t launch_llg_stage(const LlgArgs& a, hipStream_t s);
 
 }  // namespace demag

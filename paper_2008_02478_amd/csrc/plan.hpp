@@ -139,6 +139,8 @@ struct FwdArgs {
   float2* T; const float2* tw;
   int nx, ny, nz, nTiles, Kx, yg;
   int nb; const long long* moff; const float* ms_mesh; size_t Tb; const int* gid;
+  // second sublattice (nullptr: none): the input is (ms m + ms2 m2) / 2
+  const float* m2; float ms2;
 };
 
 struct MidArgs {
@@ -157,6 +159,24 @@ struct InvArgs {
   // s = per-cell Ms (or the scalar) and beta = beta_scale * beta_ptr[member]
   const float* aux; const double* beta_ptr; double beta_scale; const float* Ms; float ms; int scale_out;
   int nb; const long long* moff; const float* ms_mesh; size_t Tb; const int* gid;
+};
+
+// One RK4 stage of the LLG evaluation loop (k_llg.hip).
+struct LlgArgs {
+  const float* m0;     // state at the start of the step
+  const float* mi;     // stage input
+  const float* Hd;     // demagnetizing field of the stage input
+  float* acc;          // running sum of the stage slopes
+  float* next;         // next stage input (stages 0..2)
+  float* mout;         // new state (stage 3; may alias m0)
+  int nx, ny, nz;
+  unsigned pbc;        // periodic axes of the exchange Laplacian
+  float ihx2, ihy2, ihz2;
+  float cex;           // 2 A / (mu0 Ms)
+  float hx, hy, hz;    // applied field (A/m)
+  float gp;            // gamma / (1 + alpha^2)
+  float alpha, dt;
+  int stage;
 };
 
 }  // namespace demag

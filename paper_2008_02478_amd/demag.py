@@ -123,6 +123,33 @@ class DemagPlan(_Schedules):
                                        _l.ACCUMULATE if accumulate else 0, _ptr(e), _stream()))
         return (out, e) if energy else out
 
+    def field_2sub(self, mA, mB, MsA, MsB, out=None, accumulate=False, energy=False):
+        """Demagnetizing field of the mean magnetization (MsA mA + MsB mB) / 2
+        of two sublattices."""
+        self._check_vec(mA, "mA")
+        self._check_vec(mB, "mB")
+        out = torch.empty_like(mA) if out is None else out
+        self._check_vec(out, "out")
+        e = torch.empty((), dtype=torch.float64, device=self.device) if energy else None
+        _l.check(self._lib.demag_field_2sub(self._p, _ptr(mA), _ptr(mB), float(MsA), float(MsB), _ptr(out),
+                                            _l.ACCUMULATE if accumulate else 0, _ptr(e), _stream()))
+        return (out, e) if energy else out
+
+    def llg_rk4(self, m, Ms, A, alpha, dt, Hext=(0.0, 0.0, 0.0), gamma=0.0, steps=1):
+        """`steps` RK4 steps of the LLG equation in place on m (demagnetizing,
+        exchange and applied fields); returns m."""
+        self._check_vec(m, "m")
+        if getattr(self, "_llg_work", None) is None:
+            nb = ctypes.c_size_t()
+            _l.check(self._lib.demag_llg_workspace_bytes(self._p, ctypes.byref(nb)))
+            self._llg_work = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        prm = _l.LlgParams(float(Ms), float(A), float(alpha), float(gamma), float(dt),
+                           (ctypes.c_float * 3)(*[float(v) for v in Hext]))
+        for _ in range(steps):
+            _l.check(self._lib.demag_llg_rk4(self._p, _ptr(m), ctypes.byref(prm), self._aligned(self._llg_work),
+                                             _stream()))
+        return m
+
     def energy(self, m, Ms, H):
         """E = -(mu0/2) V sum Ms m . H as a 0-d float64 device tensor."""
         self._check_vec(m, "m")

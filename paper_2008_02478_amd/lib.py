@@ -14,6 +14,13 @@ TUNE_FORCE = 1
 _NAMES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOMEM: "ENOMEM", EHIP: "EHIP", ESTATE: "ESTATE"}
 
 _lib = None
+
+
+class LlgParams(ctypes.Structure):
+    """demag_llg_params of include/demag.h."""
+    _fields_ = [("Ms", ctypes.c_float), ("A", ctypes.c_float), ("alpha", ctypes.c_float),
+                ("gamma", ctypes.c_float), ("dt", ctypes.c_float), ("Hext", ctypes.c_float * 3)]
+
 _vp, _int, _uint, _dbl, _flt = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint, ctypes.c_double, ctypes.c_float
 
 _SIGS = {
@@ -35,6 +42,9 @@ _SIGS = {
     "demag_get_schedule": [_vp, _int, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int)],
     "demag_set_schedule": [_vp, _int, _int, _int, _int],
     "demag_autotune": [_vp, _vp, _vp, ctypes.c_char_p, _uint, ctypes.POINTER(_int), _vp],
+    "demag_field_2sub": [_vp, _vp, _vp, _flt, _flt, _vp, _uint, _vp, _vp],
+    "demag_llg_workspace_bytes": [_vp, ctypes.POINTER(ctypes.c_size_t)],
+    "demag_llg_rk4": [_vp, _vp, ctypes.POINTER(LlgParams), _vp, _vp],
     "demag_destroy": [_vp],
 }
 

@@ -298,3 +298,33 @@ def test_periodic_batch_rules(lib):
     assert lib.demag_setup_batch(ctypes.byref(p), k, dims, cells, orig, grp, L.PBC_X | L.PBC_Y, 4) == L.OK
     lib.demag_destroy(p)
     assert lib.demag_setup_batch(ctypes.byref(p), k, dims, cells, orig, grp, 8, 4) == L.EINVAL
+
+
+def test_llg_and_two_sublattice_host_checks(lib):
+    rc, p = setup(lib, 16, 8, 1, 5e-9, 5e-9, 3e-9, 0, 0)
+    assert rc == L.OK
+    nb = ctypes.c_size_t()
+    assert lib.demag_llg_workspace_bytes(p, ctypes.byref(nb)) == L.OK
+    assert nb.value >= 4 * 3 * 16 * 8 * 4
+    d = ctypes.c_void_p(256)
+    prm = L.LlgParams(8e5, 1.3e-11, 0.02, 0.0, 1e-13, (ctypes.c_float * 3)(0.0, 0.0, 1e4))
+    # not bound yet
+    assert lib.demag_llg_rk4(p, d, ctypes.byref(prm), d, None) == L.ESTATE
+    assert lib.demag_llg_rk4(p, None, ctypes.byref(prm), d, None) == L.EINVAL
+    assert lib.demag_llg_rk4(p, d, None, d, None) == L.EINVAL
+    assert lib.demag_field_2sub(p, d, d, 1.0, 1.0, d, 0, None, None) == L.ESTATE
+    # unbound plans report the state before argument pointers
+    assert lib.demag_field_2sub(p, d, None, 1.0, 1.0, d, 0, None, None) == L.ESTATE
+    assert lib.demag_field_2sub(None, d, d, 1.0, 1.0, d, 0, None, None) == L.EINVAL
+    bad = L.LlgParams(-1.0, 1.3e-11, 0.02, 0.0, 1e-13, (ctypes.c_float * 3)(0.0, 0.0, 0.0))
+    assert lib.demag_llg_rk4(None, d, ctypes.byref(bad), d, None) == L.EINVAL
+    lib.demag_destroy(p)
+    k = 2
+    dims = (ctypes.c_int * (3 * k))(8, 8, 1, 8, 8, 1)
+    cells = (ctypes.c_double * (3 * k))(*([1e-9] * (3 * k)))
+    q = ctypes.c_void_p()
+    assert lib.demag_setup_batch(ctypes.byref(q), k, dims, cells, None, None, 0, 0) == L.OK
+    assert lib.demag_llg_workspace_bytes(q, ctypes.byref(nb)) == L.EINVAL
+    assert lib.demag_llg_rk4(q, d, ctypes.byref(prm), d, None) == L.EINVAL
+    assert lib.demag_field_2sub(q, d, d, 1.0, 1.0, d, 0, None, None) == L.EINVAL
+    lib.demag_destroy(q)

@@ -83,3 +83,13 @@ def test_two_sublattice_input_is_mean():
 def test_gamma_matches_electron_gyromagnetic_ratio():
     # CODATA electron gyromagnetic ratio |gamma_e| = 1.76085963e11 1/(s T)
     assert abs(llg.GAMMA - conv.MU0 * 1.76085963023e11) / llg.GAMMA < 1e-8
+
+
+def test_periodic_laplacian_modes():
+    # periodic axis: exp modes cos(2 pi k i / n) with eigenvalue -(2/h^2)(1 - cos(2 pi k / n))
+    n, h, k = (10, 4, 1), (2e-9, 3e-9, 1e-9), 3
+    i = np.arange(n[0])
+    mode = np.cos(2 * math.pi * k * i / n[0])
+    m = np.broadcast_to(mode.reshape(1, 1, 1, n[0]), (3, n[2], n[1], n[0])).copy()
+    lam = -2.0 / h[0] ** 2 * (1.0 - math.cos(2 * math.pi * k / n[0]))
+    assert np.max(np.abs(llg.laplacian_neumann(m, h, (True, False, False)) - lam * m)) < 1e-9 * abs(lam)
