@@ -133,6 +133,26 @@ def bench_batch(torch, reps=10, tune=True, cache=None):
             "identical_results": bool(same), "schedules": full.schedules()}
 
 
+def bench_llg(torch, plan, m_np, steps=10):
+    """RK4 steps of the LLG equation on the benchmark mesh (demagnetizing,
+    exchange and a perpendicular applied field; four field evaluations per
+    step): time per step and per evaluation."""
+    m = torch.from_numpy(m_np).to(plan.device)
+    kw = dict(Ms=1.1e6, A=1.3e-11, alpha=0.02, dt=1e-13, Hext=(0.0, 0.0, 1e5))
+    plan.llg_rk4(m, steps=2, **kw)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    plan.llg_rk4(m, steps=steps, **kw)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    return {"workload": "RK4 steps of the LLG equation (demagnetizing + exchange + perpendicular applied field) "
+                        "on the benchmark mesh, 4 field evaluations per step",
+            "ms_per_step": ms, "us_per_evaluation": 1e3 * ms / 4, "steps": steps,
+            "params": {k: (list(v) if isinstance(v, tuple) else v) for k, v in kw.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +301,7 @@ def main():
     }
 
     out["batched_multi_mesh"] = bench_batch(torch, tune=not args.no_tune, cache=args.schedule_cache)
+    out["llg_rk4"] = bench_llg(torch, plan, m_np)
 
     if not args.no_cpu_baseline:
         from oracle import conv
