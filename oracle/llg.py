@@ -33,31 +33,36 @@ HBAR = 1.054571817e-34
 GAMMA = MU0 * G_E * MU_B / HBAR          # m / (A s)
 
 
-def laplacian_neumann(m, h):
+def laplacian_neumann(m, h, pbc=(False, False, False)):
     """6-point Laplacian of each component of m [3, nz, ny, nx] with the
-    homogeneous Neumann condition (ghost cell = boundary cell)."""
+    homogeneous Neumann condition (ghost cell = boundary cell), or periodic
+    neighbours along the axes flagged in pbc (x, y, z)."""
     m = np.asarray(m, np.float64)
     out = np.zeros_like(m)
-    for ax, hh in zip((3, 2, 1), h):          # x, y, z array axes
+    for ax, hh, per in zip((3, 2, 1), h, pbc):          # x, y, z array axes
         if m.shape[ax] == 1:
             continue
-        fwd = np.concatenate([np.take(m, range(1, m.shape[ax]), axis=ax),
-                              np.take(m, [m.shape[ax] - 1], axis=ax)], axis=ax)
-        bwd = np.concatenate([np.take(m, [0], axis=ax),
-                              np.take(m, range(0, m.shape[ax] - 1), axis=ax)], axis=ax)
+        if per:
+            fwd, bwd = np.roll(m, -1, axis=ax), np.roll(m, 1, axis=ax)
+        else:
+            fwd = np.concatenate([np.take(m, range(1, m.shape[ax]), axis=ax),
+                                  np.take(m, [m.shape[ax] - 1], axis=ax)], axis=ax)
+            bwd = np.concatenate([np.take(m, [0], axis=ax),
+                                  np.take(m, range(0, m.shape[ax] - 1), axis=ax)], axis=ax)
         out += (fwd - 2.0 * m + bwd) / (hh * hh)
     return out
 
 
-def exchange_field(m, Ms, A, h):
+def exchange_field(m, Ms, A, h, pbc=(False, False, False)):
     """H_ex = (2 A / (mu0 Ms)) lap(m)  (A/m)."""
-    return 2.0 * A / (MU0 * Ms) * laplacian_neumann(m, h)
+    return 2.0 * A / (MU0 * Ms) * laplacian_neumann(m, h, pbc)
 
 
-def effective_field(m, Ms, A, Hext, h, Nfull=None):
-    """H_eff = H_demag[Ms m] + H_ex + H_ext."""
+def effective_field(m, Ms, A, Hext, h, Nfull=None, pbc=(False, False, False)):
+    """H_eff = H_demag[Ms m] + H_ex + H_ext (Nfull: the tensor to convolve
+    with, e.g. the image-summed one of periodic boundaries)."""
     He = fft_conv(Ms * np.asarray(m, np.float64), h, Nfull)
-    He += exchange_field(m, Ms, A, h)
+    He += exchange_field(m, Ms, A, h, pbc)
     He += np.asarray(Hext, np.float64).reshape(3, 1, 1, 1)
     return He
 
@@ -68,11 +73,11 @@ def llg_rhs(m, H, alpha, gamma=GAMMA):
     return -gamma / (1.0 + alpha * alpha) * (mxH + alpha * np.cross(m, mxH, axis=0))
 
 
-def rk4_step(m, dt, Ms, A, alpha, Hext, h, gamma=GAMMA, Nfull=None):
+def rk4_step(m, dt, Ms, A, alpha, Hext, h, gamma=GAMMA, Nfull=None, pbc=(False, False, False)):
     """One classical RK4 step of the LLG equation (four field evaluations),
     then renormalization of m."""
     m = np.asarray(m, np.float64)
-    f = lambda x: llg_rhs(x, effective_field(x, Ms, A, Hext, h, Nfull), alpha, gamma)
+    f = lambda x: llg_rhs(x, effective_field(x, Ms, A, Hext, h, Nfull, pbc), alpha, gamma)
     k1 = f(m)
     k2 = f(m + 0.5 * dt * k1)
     k3 = f(m + 0.5 * dt * k2)
