@@ -42,6 +42,15 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Exchange point of a group of T lanes: wavefront ordering for groups within
+// one wavefront; a workgroup barrier for groups spanning several wavefronts
+// (then every lane of the workgroup must run the same transforms).
+template <int T>
+__device__ __forceinline__ void group_sync() {
+  if constexpr (T > 64) __syncthreads();
+  else wave_sync();
+}
+
 // exp(-2 pi i m / N) (forward) or its conjugate (INV), N a power of two <= 4096.
 template <bool INV>
 __device__ __forceinline__ float2 twiddle(const float2* __restrict__ tw, int m, int log2N) {
@@ -196,7 +205,7 @@ __device__ __forceinline__ void stockham_stage(float2 (&v)[R], float2* __restric
 #pragma unroll
     for (int r = 0; r < RS; ++r) a[i][r] = lds[swz<M, R>(b + r * (M / RS))];
   }
-  wave_sync();
+  group_sync<T>();
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int k = (t + T * i) & (NS - 1);
@@ -221,7 +230,7 @@ __device__ __forceinline__ void stockham_stage(float2 (&v)[R], float2* __restric
 #pragma unroll
       for (int r = 0; r < RS; ++r) lds[swz<M, R>(base + r * NS)] = a[i][r];
     }
-    wave_sync();
+    group_sync<T>();
   }
 }
 
@@ -238,19 +247,23 @@ __device__ __forceinline__ void stockham_rest(float2 (&v)[R], float2* __restrict
 
 // Group FFT of M points, lane t in [0, M/R) of its group, stride-T layout in
 // and out.  lds: M points of scratch owned by this group (unused when M == R);
-// tab: the stage twiddle table in LDS.  Unnormalized in both directions.
+// tab: the stage twiddle table in LDS.  Unnormalized in both directions.  A
+// group of more than 64 lanes exchanges through workgroup barriers.
 template <int M, int R, bool INV>
 __device__ __forceinline__ void group_fft(float2 (&v)[R], float2* __restrict__ lds, int t,
                                           const float2* __restrict__ tab) {
   static_assert(M % R == 0, "R must divide M");
   constexpr int T = M / R;
-  static_assert(T <= 64 && (64 % T) == 0, "a group must fit in one wavefront");
+  static_assert((T <= 64 && (64 % T) == 0) || T % 64 == 0, "a group is part of a wavefront or whole wavefronts");
   dft<R, INV>(v);
   if constexpr (M > R) {
+    // a group spanning wavefronts waits until every wavefront has finished
+    // reading this scratch (the previous transform's last stage)
+    if constexpr (T > 64) __syncthreads();
     // first stage output index b*R + r for butterfly b = t
 #pragma unroll
     for (int r = 0; r < R; ++r) lds[swz<M, R>(t * R + r)] = v[r];
-    wave_sync();
+    group_sync<T>();
     stockham_rest<M, R, R, INV, 0>(v, lds, t, tab);
   }
 }

@@ -206,7 +206,7 @@ k_mid(MidArgs a) {
 
   const int tid = threadIdx.x;
   const bool lane_act = tid < NT;
-  const int job = (T == 64) ? __builtin_amdgcn_readfirstlane(tid / T) : tid / T;
+  const int job = (T >= 64) ? __builtin_amdgcn_readfirstlane(tid / T) : tid / T;
   const int t = tid % T;
   const int w = job / NRES, r = job % NRES;
   const int kx = tile * TILE + half * KW + w;

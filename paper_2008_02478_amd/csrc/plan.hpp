@@ -27,9 +27,11 @@ constexpr int line_lds_points(int M) { return M + (M >> line_pad_shift(line_radi
 
 // Radices the middle pass may use for its M-point y lines (M = Ny/2): the
 // default, plus the alternatives the schedule tuner may pick from for the
-// long lines (4 to 64 lanes per line, at most 16 points per lane).
+// long lines (4 to 64 lanes per line, at most 16 points per lane; radix 8 for
+// 1024-point lines spans two wavefronts per line).
 constexpr bool mid_radix_ok(int M, int R) {
   if (R == line_radix(M)) return true;
+  if (M == 1024) return R == 8;      // 128 lanes per line: two wavefronts, barrier exchanges
   if (M != 256 && M != 512) return false;
   return (R == 4 || R == 8 || R == 16) && M / R <= 64;
 }

@@ -21,10 +21,12 @@ def torch():
 
 
 # (mesh, cell): y lines of 256 points (radix 4 / 8 / 16), of 512 points
-# (radix 8 / 16), and a short-line mesh with several z planes per x row
+# (radix 8 / 16), of 1024 points (radix 16, and radix 8 with lines spanning
+# two wavefronts), and a short-line mesh with several z planes per x row
 CASES = [
     ((150, 200, 3), (2e-9, 2e-9, 1e-9)),
     ((40, 300, 2), (5e-9, 5e-9, 3e-9)),
+    ((40, 600, 2), (4e-9, 2e-9, 3e-9)),
     ((70, 30, 5), (3e-9, 3e-9, 2e-9)),
 ]
 
