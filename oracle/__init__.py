@@ -18,6 +18,9 @@ Contents
   llg.py     a minimal evaluation loop: exchange and applied fields, the LLG
              equation (Sec. 2, Eq. 1), RK4 steps (Sec. 7), the two-sublattice
              demagnetizing input (Sec. 6).
+  oersted.py Oersted field of a current density, H = K * J (Table 1,
+             Oersted row; Sec. 4): the cell-averaged Biot-Savart kernel, its
+             direct sum and its zero-padded FFT convolution.
 """
 from .newell import (COMPONENTS, newell_f, newell_g, newell_near, gl_far,
                      tensor_at, tensor_octant, tensor_full)
