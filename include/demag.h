@@ -191,6 +191,33 @@ int demag_llg_workspace_bytes(const demag_plan* plan, size_t* bytes);
  * parameters, Ms <= 0, dt <= 0, A < 0 or alpha < 0; single-mesh plans. */
 int demag_llg_rk4(const demag_plan* plan, float* d_m, const demag_llg_params* params, void* d_work, void* stream);
 
+/* Oersted field of a current density (Table 1, Oersted row; Sec. 4: the
+ * field is a convolution sum of the current density with an Oersted kernel):
+ *   H_t = scale / (4 pi) sum_s J_s x g(r_t - r_s),
+ * g(d) the field integral of a cuboid cell carrying a uniform unit current
+ * density, averaged over the target cell at offset d,
+ *   g(d) = 1/V int_target int_source (r - r') / |r - r'|^3 dV' dV,
+ * built in FP64 at set-up (reduced to one-dimensional integrals of Newell's f
+ * near the source, Gauss-Legendre quadrature of the defining integral
+ * beyond).  The field passes are those of demag_field with this kernel's
+ * product, H^ = i (P x J^) per frequency.  J is SoA [3][nz][ny][nx] FP32 in
+ * A/m^2 (scale = 1) and H is in A/m; open boundaries only.
+ *
+ * demag_setup_oersted: as demag_setup, same size limits, no periodic axes;
+ * bind with demag_buffer_bytes / demag_bind as any plan.  An Oersted plan is
+ * refused (DEMAG_EINVAL) by demag_field, _2sub, _energy, _backward and the
+ * LLG calls; schedules and the tuner apply as for a demagnetizing plan.
+ *
+ * demag_oersted_field: H = scale K*J, or H += scale K*J with
+ * DEMAG_ACCUMULATE; only enqueues work (graph-capturable).  J -> H is
+ * self-adjoint (K_ab(d) = K_ba(-d)), so this call is also its own backward:
+ * d<G, H[J]>/dJ = scale K*G.  DEMAG_EINVAL for NULL buffers, unknown flags,
+ * a non-finite scale or a plan that is not an Oersted plan; DEMAG_ESTATE
+ * before demag_bind. */
+int demag_setup_oersted(demag_plan** out, int nx, int ny, int nz, double dx, double dy, double dz);
+int demag_oersted_field(const demag_plan* plan, const float* d_J, float scale, float* d_H, unsigned flags,
+                        void* stream);
+
 /* Launch schedules.  Each plan has parts: one per group of identical
  * independent meshes (a single-mesh plan has one), then one per coupled
  * group.  A part's schedule is its launch shape:
@@ -198,7 +225,8 @@ int demag_llg_rk4(const demag_plan* plan, float* d_m, const demag_llg_params* pa
  *   kw    kx lines per workgroup of the middle (y) pass: 2, 4 or 8,
  *   radix points per lane of its y line FFTs (Ny/2 points per line): the
  *         default for the length, or 4 / 8 / 16 for Ny/2 of 256 and 512 when
- *         that leaves at most 64 lanes per line.
+ *         that leaves at most 64 lanes per line, or 8 for Ny/2 = 1024 (128
+ *         lanes, a line spanning two wavefronts).
  * All schedules compute the same convolution (Sec. 3, Eq. 4); they differ
  * only in speed and FP32 rounding order.  Host only. */
 int demag_schedule_count(const demag_plan* plan, int* nparts);

@@ -62,6 +62,7 @@ struct demag_plan {
   std::vector<Sub> subs;
   std::vector<Group> groups;
   bool batch = false;
+  bool oersted = false;              // Oersted-field plan (demag_setup_oersted)
   std::vector<long long> offsets;    // float offset of each mesh in concatenated buffers
   size_t total_floats = 0;
   bool bound = false;
@@ -186,7 +187,7 @@ void layout(demag_plan* p) {
     const Geom& g = s.g;
     const size_t nb = s.members.size();
     s.k_off = kb;
-    kb += align256((size_t)6 * g.Kzh * g.Kx * (g.Kyp + 1) * sizeof(float));   // rows, then KN
+    kb += align256((size_t)kernel_comps(g) * g.Kzh * g.Kx * (g.Kyp + 1) * sizeof(float));   // rows, then KN
     s.tab_off = kb;
     kb += align256(nb * sizeof(long long)) + align256(nb * sizeof(int));
     s.t_off = wb;
@@ -411,6 +412,25 @@ int build_spectrum(const Geom& g, float* d_K, hipStream_t s) {
       gl.w[b][i] = 0.5 * w[i];
     }
   }
+  // path rule of the Oersted kernel's near offsets: QN_NODES Gauss-Legendre
+  // nodes on each of the panels [2^-(p+1), 2^-p], p < QN_PANELS, and
+  // [0, 2^-QN_PANELS] of [0, 1]
+  constexpr int QN_PANELS = 24, QN_NODES = 20, QN = (QN_PANELS + 1) * QN_NODES;
+  std::vector<double> qrule;
+  const bool oersted = g.kind == KERNEL_OERSTED;
+  if (oersted) {
+    double x[QN_NODES], w[QN_NODES];
+    gauss_legendre(QN_NODES, x, w);
+    qrule.resize(2 * QN);
+    for (int p = 0; p <= QN_PANELS; ++p) {
+      const double hi = std::ldexp(1.0, -p), lo = p == QN_PANELS ? 0.0 : hi / 2;
+      for (int i = 0; i < QN_NODES; ++i) {
+        qrule[p * QN_NODES + i] = lo + (hi - lo) * 0.5 * (1.0 + x[i]);
+        qrule[QN + p * QN_NODES + i] = (hi - lo) * 0.5 * w[i];
+      }
+    }
+  }
+  const int nc = kernel_comps(g);
   const size_t s0 = (size_t)g.nz * g.ny * g.nx;
   const size_t s1 = (size_t)g.nz * g.ny * g.Kx;
   const size_t s2 = (size_t)g.nz * g.Kyh * g.Kx;
@@ -421,13 +441,17 @@ int build_spectrum(const Geom& g, float* d_K, hipStream_t s) {
   int rc = DEMAG_OK;
   hipError_t e;
   do {
-    if (hipMalloc(&bufA, 6 * smax * sizeof(double)) != hipSuccess ||
-        hipMalloc(&bufB, 6 * smax * sizeof(double)) != hipSuccess ||
-        hipMalloc(&d_trig, trig.size() * sizeof(double)) != hipSuccess) {
+    if (hipMalloc(&bufA, nc * smax * sizeof(double)) != hipSuccess ||
+        hipMalloc(&bufB, nc * smax * sizeof(double)) != hipSuccess ||
+        hipMalloc(&d_trig, (trig.size() + qrule.size()) * sizeof(double)) != hipSuccess) {
       rc = fail(DEMAG_ENOMEM, "demag_bind: set-up temporaries could not be allocated"); break;
     }
     if ((e = hipMemcpyAsync(d_trig, trig.data(), trig.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess) {
       rc = fail_hip(e, "trig upload"); break;
+    }
+    if (oersted && (e = hipMemcpyAsync(d_trig + trig.size(), qrule.data(), qrule.size() * sizeof(double),
+                                       hipMemcpyHostToDevice, s)) != hipSuccess) {
+      rc = fail_hip(e, "rule upload"); break;
     }
     const double* cs[3];
     const double* sn[3];
@@ -435,15 +459,19 @@ int build_spectrum(const Geom& g, float* d_K, hipStream_t s) {
       cs[a] = d_trig + (size_t)(2 * a) * Nmax;
       sn[a] = d_trig + (size_t)(2 * a + 1) * Nmax;
     }
-    // component order xx yy zz xy xz yz; odd along x: xy xz; y: xy yz; z: xz yz
-    if ((e = launch_tensor(bufA, g, gl, s)) != hipSuccess) { rc = fail_hip(e, "tensor kernel"); break; }
-    if ((e = launch_axis(bufA, bufB, g.nz * g.ny, g.nx, g.Kx, 1, g.Nx, 0x18u, cs[0], sn[0], s)) != hipSuccess) {
+    // demagnetizing tensor: component order xx yy zz xy xz yz; odd along x:
+    // xy xz; y: xy yz; z: xz yz.  Oersted kernel: x y z, each odd along its own axis.
+    const unsigned odd[3] = {oersted ? 0x1u : 0x18u, oersted ? 0x2u : 0x28u, oersted ? 0x4u : 0x30u};
+    e = oersted ? launch_oe_tensor(bufA, g, gl, d_trig + trig.size(), d_trig + trig.size() + QN, QN, s)
+                : launch_tensor(bufA, g, gl, s);
+    if (e != hipSuccess) { rc = fail_hip(e, "tensor kernel"); break; }
+    if ((e = launch_axis(bufA, bufB, nc, g.nz * g.ny, g.nx, g.Kx, 1, g.Nx, odd[0], cs[0], sn[0], s)) != hipSuccess) {
       rc = fail_hip(e, "x transform"); break;
     }
-    if ((e = launch_axis(bufB, bufA, g.nz, g.ny, g.Kyh, g.Kx, g.Ny, 0x28u, cs[1], sn[1], s)) != hipSuccess) {
+    if ((e = launch_axis(bufB, bufA, nc, g.nz, g.ny, g.Kyh, g.Kx, g.Ny, odd[1], cs[1], sn[1], s)) != hipSuccess) {
       rc = fail_hip(e, "y transform"); break;
     }
-    if ((e = launch_axis(bufA, bufB, 1, g.nz, g.Kzh, g.Kyh * g.Kx, g.Nz, 0x30u, cs[2], sn[2], s)) != hipSuccess) {
+    if ((e = launch_axis(bufA, bufB, nc, 1, g.nz, g.Kzh, g.Kyh * g.Kx, g.Nz, odd[2], cs[2], sn[2], s)) != hipSuccess) {
       rc = fail_hip(e, "z transform"); break;
     }
     if ((e = launch_pack(bufB, d_K, g, s)) != hipSuccess) { rc = fail_hip(e, "pack"); break; }
@@ -724,7 +752,8 @@ std::string part_key(const demag_plan* p, int i, const std::string& dev) {
   char buf[160];
   if (i < (int)p->subs.size()) {
     const Sub& sb = p->subs[i];
-    std::snprintf(buf, sizeof buf, "|mesh %dx%dx%d nb=%d", sb.g.nx, sb.g.ny, sb.g.nz, (int)sb.members.size());
+    std::snprintf(buf, sizeof buf, "|%s %dx%dx%d nb=%d", sb.g.kind == KERNEL_OERSTED ? "oersted" : "mesh", sb.g.nx,
+                  sb.g.ny, sb.g.nz, (int)sb.members.size());
   } else {
     const Group& G = p->groups[i - p->subs.size()];
     std::snprintf(buf, sizeof buf, "|layers %dx%d planes=%d", G.g.nx, G.g.ny, (int)G.planes.size());
@@ -756,6 +785,27 @@ int demag_setup(demag_plan** out, int nx, int ny, int nz, double dx, double dy, 
   p->subs.push_back(sb);
   p->offsets = {0};
   p->total_floats = (size_t)3 * nx * ny * nz;
+  layout(p);
+  *out = p;
+  return DEMAG_OK;
+}
+
+int demag_setup_oersted(demag_plan** out, int nx, int ny, int nz, double dx, double dy, double dz) {
+  if (!out) return fail(DEMAG_EINVAL, "demag_setup_oersted: out is NULL");
+  *out = nullptr;
+  Geom g;
+  int rc = make_geom(nx, ny, nz, dx, dy, dz, 0u, 0, g, "demag_setup_oersted");
+  if (rc != DEMAG_OK) return rc;
+  g.kind = KERNEL_OERSTED;
+  demag_plan* p = new (std::nothrow) demag_plan;
+  if (!p) return fail(DEMAG_ENOMEM, "demag_setup_oersted: out of host memory");
+  Sub sb;
+  sb.g = g;
+  sb.members = {0};
+  p->subs.push_back(sb);
+  p->offsets = {0};
+  p->total_floats = (size_t)3 * nx * ny * nz;
+  p->oersted = true;
   layout(p);
   *out = p;
   return DEMAG_OK;
@@ -917,6 +967,7 @@ int demag_bind(demag_plan* p, void* d_kernel, void* d_work, void* stream) {
 int demag_field(const demag_plan* p, const float* d_m, const float* d_Ms, float Ms, float* d_H, unsigned flags,
                 double* d_energy, void* stream) {
   if (!p) return fail(DEMAG_EINVAL, "demag_field: plan is NULL");
+  if (p->oersted) return fail(DEMAG_EINVAL, "demag_field: an Oersted plan (use demag_oersted_field)");
   if (p->batch) return fail(DEMAG_EINVAL, "demag_field: batch plans use demag_field_batch");
   if (!p->bound) return fail(DEMAG_ESTATE, "demag_field: plan is not bound");
   if (!d_m || !d_H) return fail(DEMAG_EINVAL, "demag_field: NULL m or H");
@@ -925,9 +976,21 @@ int demag_field(const demag_plan* p, const float* d_m, const float* d_Ms, float 
   return run_field(p, d_m, d_Ms, Ms, nullptr, d_H, flags, d_energy, static_cast<hipStream_t>(stream));
 }
 
+int demag_oersted_field(const demag_plan* p, const float* d_J, float scale, float* d_H, unsigned flags,
+                        void* stream) {
+  if (!p) return fail(DEMAG_EINVAL, "demag_oersted_field: plan is NULL");
+  if (!p->oersted) return fail(DEMAG_EINVAL, "demag_oersted_field: not an Oersted plan (use demag_setup_oersted)");
+  if (!p->bound) return fail(DEMAG_ESTATE, "demag_oersted_field: plan is not bound");
+  if (!d_J || !d_H) return fail(DEMAG_EINVAL, "demag_oersted_field: NULL J or H");
+  if (flags & ~(unsigned)DEMAG_ACCUMULATE) return fail(DEMAG_EINVAL, "demag_oersted_field: unknown flags");
+  if (!std::isfinite(scale)) return fail(DEMAG_EINVAL, "demag_oersted_field: scale is not finite");
+  return run_field(p, d_J, nullptr, scale, nullptr, d_H, flags, nullptr, static_cast<hipStream_t>(stream));
+}
+
 int demag_field_2sub(const demag_plan* p, const float* d_mA, const float* d_mB, float MsA, float MsB, float* d_H,
                      unsigned flags, double* d_energy, void* stream) {
   if (!p) return fail(DEMAG_EINVAL, "demag_field_2sub: plan is NULL");
+  if (p->oersted) return fail(DEMAG_EINVAL, "demag_field_2sub: an Oersted plan");
   if (p->batch) return fail(DEMAG_EINVAL, "demag_field_2sub: single-mesh plans only");
   if (!p->bound) return fail(DEMAG_ESTATE, "demag_field_2sub: plan is not bound");
   if (!d_mA || !d_mB || !d_H) return fail(DEMAG_EINVAL, "demag_field_2sub: NULL mA, mB or H");
@@ -954,6 +1017,7 @@ int demag_field_batch(const demag_plan* p, const float* d_m, const float* d_Ms_m
 int demag_energy(const demag_plan* p, const float* d_m, const float* d_Ms, float Ms, const float* d_H,
                  double* d_energy, void* stream) {
   if (!p) return fail(DEMAG_EINVAL, "demag_energy: plan is NULL");
+  if (p->oersted) return fail(DEMAG_EINVAL, "demag_energy: an Oersted plan");
   if (p->batch) return fail(DEMAG_EINVAL, "demag_energy: single-mesh plans only");
   if (!p->bound) return fail(DEMAG_ESTATE, "demag_energy: plan is not bound");
   if (!d_m || !d_H || !d_energy) return fail(DEMAG_EINVAL, "demag_energy: NULL argument");
@@ -972,6 +1036,8 @@ int demag_energy(const demag_plan* p, const float* d_m, const float* d_Ms, float
 int demag_backward(const demag_plan* p, const float* d_G, const float* d_Ms, float Ms, const float* d_H,
                    const double* d_gE, float* d_grad_m, unsigned flags, void* stream) {
   if (!p) return fail(DEMAG_EINVAL, "demag_backward: plan is NULL");
+  if (p->oersted) return fail(DEMAG_EINVAL, "demag_backward: an Oersted plan (its operator is self-adjoint: "
+                                            "demag_oersted_field is its own backward)");
   if (p->batch) return fail(DEMAG_EINVAL, "demag_backward: batch plans use demag_backward_batch");
   if (!p->bound) return fail(DEMAG_ESTATE, "demag_backward: plan is not bound");
   if (!d_G || !d_grad_m) return fail(DEMAG_EINVAL, "demag_backward: NULL G or grad_m");
@@ -1090,6 +1156,7 @@ int demag_autotune(demag_plan* p, const float* d_m, float* d_H, const char* cach
 
 int demag_llg_workspace_bytes(const demag_plan* p, size_t* bytes) {
   if (!p || !bytes) return fail(DEMAG_EINVAL, "demag_llg_workspace_bytes: NULL argument");
+  if (p->oersted) return fail(DEMAG_EINVAL, "demag_llg_workspace_bytes: an Oersted plan");
   if (p->batch) return fail(DEMAG_EINVAL, "demag_llg_workspace_bytes: single-mesh plans only");
   const Geom& g = p->subs[0].g;
   *bytes = 4 * align256((size_t)3 * g.nx * g.ny * g.nz * sizeof(float));
@@ -1098,6 +1165,7 @@ int demag_llg_workspace_bytes(const demag_plan* p, size_t* bytes) {
 
 int demag_llg_rk4(const demag_plan* p, float* d_m, const demag_llg_params* prm, void* d_work, void* stream) {
   if (!p || !d_m || !prm || !d_work) return fail(DEMAG_EINVAL, "demag_llg_rk4: NULL argument");
+  if (p->oersted) return fail(DEMAG_EINVAL, "demag_llg_rk4: an Oersted plan");
   if (p->batch) return fail(DEMAG_EINVAL, "demag_llg_rk4: single-mesh plans only");
   if (!p->bound) return fail(DEMAG_ESTATE, "demag_llg_rk4: plan is not bound");
   if (!aligned(d_work)) return fail(DEMAG_EINVAL, "demag_llg_rk4: workspace must be 256-byte aligned");

@@ -176,6 +176,8 @@ __device__ __forceinline__ Tv block_sum(Tv v, Tv* red) {
 // MODE 1: y FFT only; spectra to S[c][kz][kx][ky] with ky ordered by residue
 //         (r * NY/2 + k' for ky = 2k' + r).
 // MODE 2: inverse y FFT only, from S.
+// MODE 3: as MODE 0 with the Oersted kernel: H^ = i (P x J^), P the real
+//         3-row spectrum (x even in ky and kz, y odd in ky, z odd in kz).
 // R: points per lane of the M-point y lines (M / R lanes per line).
 template <int LNY, int KW, bool ENERGY, int MODE = 0, int R = mid_radix_of(LNY)>
 __global__ void __launch_bounds__(mid_threads(LNY, KW, R)) __attribute__((amdgpu_waves_per_eu(R >= 16 ? 2 : 4, 8)))
@@ -201,7 +203,9 @@ k_mid(MidArgs a) {
   const int half = lg % halves;
   const int kzi = (lg / halves) % a.Nz;
   const int tile = lg / (halves * a.Nz);
-  const int kz = MODE == 0 ? kz_of(kzi, a.Nz) : kzi;
+  constexpr bool PROD = MODE == 0 || MODE == 3;   // kernel product in this pass
+  constexpr int NKC = MODE == 3 ? 3 : 6;          // kernel rows per (kz, kx)
+  const int kz = PROD ? kz_of(kzi, a.Nz) : kzi;
   const int ny = a.ny;
 
   const int tid = threadIdx.x;
@@ -227,8 +231,8 @@ k_mid(MidArgs a) {
   if constexpr (M > R) fill_stage_table<M, R>(tab, a.tw, tid, blockDim.x);
   const float2 rbase = twiddle<false>(a.tw, t, ilog2(2 * M));
 
-  // The kernel spectrum of this workgroup (KW consecutive kx lines of 6 rows
-  // of KYP floats, contiguous in K[kz][kx][c][ky], plus their 6 KW Nyquist
+  // The kernel spectrum of this workgroup (KW consecutive kx lines of NKC rows
+  // of KYP floats, contiguous in K[kz][kx][c][ky], plus their NKC KW Nyquist
   // entries) is requested with the components and held in registers through
   // the forward transforms, so its latency overlaps them; it moves to LDS
   // just before the product.  In LDS a row (pitch KLP) holds the even-ky
@@ -237,8 +241,8 @@ k_mid(MidArgs a) {
   constexpr int KLP = NRES == 2 ? KYP + 4 : KYP;
   constexpr int OH = KYP / 2 + 2;
   constexpr int NTHK = mid_threads(LNY, KW, R);
-  constexpr int KF4 = KW * 6 * KYP / 4;           // float4 per workgroup block
-  constexpr int KIT = MODE == 0 ? (KF4 + NTHK - 1) / NTHK : 1;
+  constexpr int KF4 = KW * NKC * KYP / 4;         // float4 per workgroup block
+  constexpr int KIT = PROD ? (KF4 + NTHK - 1) / NTHK : 1;
   const int kzf = (kz <= a.Nz / 2) ? kz : a.Nz - kz;
   const int kx0 = tile * TILE + half * KW;
   float4 kp[KIT];
@@ -276,16 +280,16 @@ k_mid(MidArgs a) {
     }
     // kernel rows after the components: waits for the components then leave
     // the kernel rows in flight (memory counters retire in issue order)
-    if constexpr (MODE == 0) {
-      const float4* Kb4 = reinterpret_cast<const float4*>(a.K + ((size_t)kzf * a.Kx + kx0) * 6 * KYP);
+    if constexpr (PROD) {
+      const float4* Kb4 = reinterpret_cast<const float4*>(a.K + ((size_t)kzf * a.Kx + kx0) * NKC * KYP);
 #pragma unroll
       for (int i = 0; i < KIT; ++i) {
         const int e = tid + i * NTHK;
-        const bool in = e < KF4 && kx0 + e / (6 * KYP / 4) < a.Kx;
+        const bool in = e < KF4 && kx0 + e / (NKC * KYP / 4) < a.Kx;
         kp[i] = in ? Kb4[e] : make_float4(0.f, 0.f, 0.f, 0.f);
       }
-      if (NY >= 4 && tid < 6 * KW && kx0 + tid / 6 < a.Kx)
-        knv = a.K[(size_t)6 * a.Kzh * a.Kx * KYP + ((size_t)kzf * a.Kx + kx0) * 6 + tid];
+      if (NY >= 4 && tid < NKC * KW && kx0 + tid / NKC < a.Kx)
+        knv = a.K[(size_t)NKC * a.Kzh * a.Kx * KYP + ((size_t)kzf * a.Kx + kx0) * NKC + tid];
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -326,11 +330,11 @@ k_mid(MidArgs a) {
     }
   }
 
-  // point-wise product with the real, symmetric kernel spectrum.  In LDS each
-  // kernel row is split by the parity of ky (the parity of a job's folded ky
-  // is its residue r), so the lanes of a job read consecutive words.
+  // point-wise product with the real kernel spectrum.  In LDS each kernel row
+  // is split by the parity of ky (the parity of a job's folded ky is its
+  // residue r), so the lanes of a job read consecutive words.
   float* const kl = reinterpret_cast<float*>(smem);   // aliases stage and FFT scratch
-  if constexpr (MODE == 0) {
+  if constexpr (PROD) {
     __syncthreads();   // every job is done with its forward FFT scratch
 #pragma unroll
     for (int i = 0; i < KIT; ++i) {
@@ -346,13 +350,13 @@ k_mid(MidArgs a) {
         }
       }
     }
-    if (NY >= 4 && tid < 6 * KW) kl[tid * KLP + KYP / 2] = knv;
+    if (NY >= 4 && tid < NKC * KW) kl[tid * KLP + KYP / 2] = knv;
     __syncthreads();
   }
   double e = 0.0;
-  if (lane_act && MODE == 0) {
+  if (lane_act && PROD) {
     const float sz = (kz <= a.Nz / 2) ? 1.f : -1.f;
-    const float* const Kb = kl + w * 6 * KLP;
+    const float* const Kb = kl + w * NKC * KLP;
     const float wkx = (kx == 0 || 2 * kx == a.Nx) ? 1.f : 2.f;
     float ef = 0.f;
 #pragma unroll
@@ -366,6 +370,20 @@ k_mid(MidArgs a) {
       int ki = NRES == 2 ? (r ? OH : 0) + (kyf >> 1) : kyf;
       if constexpr (NY == 4) ki = kyf == 2 ? KYP / 2 : ki;
       const float sy = lo ? 1.f : -1.f;
+      if constexpr (MODE == 3) {
+        // H^ = i (P x J^), P real: i (a + i b) = -b + i a
+        const float px = Kb[0 * KLP + ki];
+        const float py = sy * Kb[1 * KLP + ki];
+        const float pz = sz * Kb[2 * KLP + ki];
+        const float2 jx = v[0][j], jy = v[1][j], jz = v[2][j];
+        const float2 cx = make_float2(py * jz.x - pz * jy.x, py * jz.y - pz * jy.y);
+        const float2 cy = make_float2(pz * jx.x - px * jz.x, pz * jx.y - px * jz.y);
+        const float2 cz = make_float2(px * jy.x - py * jx.x, px * jy.y - py * jx.y);
+        v[0][j] = make_float2(-cx.y, cx.x);
+        v[1][j] = make_float2(-cy.y, cy.x);
+        v[2][j] = make_float2(-cz.y, cz.x);
+        continue;
+      }
       const float kxx = Kb[0 * KLP + ki];
       const float kyy = Kb[1 * KLP + ki];
       const float kzz = Kb[2 * KLP + ki];
@@ -382,7 +400,7 @@ k_mid(MidArgs a) {
     }
     if (ENERGY && valid) e = (double)(wkx * ef);
   }
-  if constexpr (MODE == 0) __syncthreads();   // kernel rows read before the scratch is reused
+  if constexpr (PROD) __syncthreads();   // kernel rows read before the scratch is reused
   if (lane_act) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -687,7 +705,7 @@ static hipError_t mid_launch(const Geom& g, const MidArgs& a, hipStream_t s) {
   const size_t st = (size_t)3 * g.ny * (KW + 1) * sizeof(float2);   // staging of the three components
   if (st > lds) lds = st;
   const size_t klp = NRES == 2 ? kernel_row_pitch(NY) + 4 : kernel_row_pitch(NY);
-  const size_t kr = MODE == 0 ? (size_t)KW * 6 * klp * sizeof(float) : 0;   // kernel rows
+  const size_t kr = (MODE == 0 || MODE == 3) ? (size_t)KW * (MODE == 3 ? 3 : 6) * klp * sizeof(float) : 0;
   if (kr > lds) lds = kr;
   lds += tab_points<M, R>() * sizeof(float2);
   hipError_t e = prep_lds(k_mid<LNY, KW, ENERGY, MODE, R>, lds);
@@ -699,7 +717,8 @@ static hipError_t mid_launch(const Geom& g, const MidArgs& a, hipStream_t s) {
 }
 
 // mode 0: the pipelined pass (energy partials when a.epart is set);
-// 1 / 2: the split y passes of coupled layers
+// 1 / 2: the split y passes of coupled layers; 3: the pipelined pass with the
+// Oersted kernel
 template <int LNY, int KW, int R>
 static hipError_t mid_mode(const Geom& g, const MidArgs& a, int mode, hipStream_t s) {
   if constexpr (!mid_schedule_ok(LNY > 0 ? (1 << LNY) / 2 : 1, KW, R)) {
@@ -707,6 +726,7 @@ static hipError_t mid_mode(const Geom& g, const MidArgs& a, int mode, hipStream_
   } else {
   if (mode == 1) return mid_launch<LNY, KW, false, 1, R>(g, a, s);
   if (mode == 2) return mid_launch<LNY, KW, false, 2, R>(g, a, s);
+  if (mode == 3) return mid_launch<LNY, KW, false, 3, R>(g, a, s);
   return a.epart ? mid_launch<LNY, KW, true, 0, R>(g, a, s) : mid_launch<LNY, KW, false, 0, R>(g, a, s);
   }
 }
@@ -751,7 +771,9 @@ static hipError_t mid_dispatch(const Geom& g, const MidArgs& a, int mode, hipStr
   }
 }
 
-hipError_t launch_mid(const Geom& g, const MidArgs& a, hipStream_t s) { return mid_dispatch(g, a, 0, s); }
+hipError_t launch_mid(const Geom& g, const MidArgs& a, hipStream_t s) {
+  return mid_dispatch(g, a, g.kind == KERNEL_OERSTED ? 3 : 0, s);
+}
 
 // y passes without the kernel product (coupled layers): mode 1 forward into
 // S, mode 2 inverse from S

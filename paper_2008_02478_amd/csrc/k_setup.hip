@@ -15,8 +15,17 @@
 //  k_pack     : scale by -s/(Nx Ny Nz) (s = -1 for off-diagonal components,
 //               from (-i)^2) and store FP32 in the layout read by the middle
 //               pass, K[kz][kx][component][ky].
+//
+// The Oersted kernel (Table 1, Oersted row; Sec. 4) takes the same route with
+// three components: g(d), the field of a cuboid cell of unit current density
+// averaged over the target cell at offset d (H = 1/(4 pi) J x g), built by
+// k_oe_near (|d| < 3 h_max) and k_oe_far; g_a is odd along axis a only, so
+// its spectrum is -i times a real octant, packed as 1/(4 pi Nx Ny Nz) times
+// that real part.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <climits>
+#include <cmath>
 #include "plan.hpp"
 
 namespace demag {
@@ -138,14 +147,109 @@ __global__ void k_tensor(double* __restrict__ out, int nx, int ny, int nz, doubl
   for (int q = 0; q < 6; ++q) out[q * cnt + idx] = S[q];
 }
 
+// ---------------------------------------------------------------------------
+// Oersted kernel g(d) = 1/V int_target int_source (r - r') / |r - r'|^3
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool oe_near(double X, double Y, double Z, double hmax) {
+  return sqrt(X * X + Y * Y + Z * Z) / hmax < 3.0;
+}
+
+// Q(X, Y, Z) = int_0^X f(s, Y, Z) ds with Newell's f (even in s, so Q is odd
+// in X): the rule (qs, qw) on [0, 1], panels that halve towards s = 0, where
+// f's only non-analytic point on the path lies.  d/dX d^2/dY^2 d^2/dZ^2 Q = 1/R.
+__device__ double q_path(double X, double Y, double Z, const double* __restrict__ qs,
+                         const double* __restrict__ qw, int nq) {
+  const double ax = fabs(X);
+  if (ax == 0.0) return 0.0;
+  double acc = 0.0;
+  for (int i = 0; i < nq; ++i) acc += qw[i] * nf(ax * qs[i], Y, Z);
+  return (X < 0.0 ? -ax : ax) * acc;
+}
+
+// Near offsets (|d| < 3 h_max), one workgroup each over the box bx x by x bz
+// of candidates: (r - r')_a / |r - r'|^3 = d/dr'_a (1/|r - r'|), so
+//   g_a = -(1/V) sum_{i,j,k} w_i w_j w_k Q(A + i h_a, B + j h_b, C + k h_c),
+// w_0 = -2, w_{+-1} = 1, with (A, B, C) the offset taken along (a, b, c), b
+// and c the other two axes.  81 lanes take one (component, stencil point)
+// each; lane c sums its component's 27 terms in a fixed order.
+__global__ void __launch_bounds__(128) k_oe_near(double* __restrict__ out, int nx, int ny, int nz, double dx,
+                                                 double dy, double dz, int bx, int by, const double* __restrict__ qs,
+                                                 const double* __restrict__ qw, int nq) {
+  const int b = blockIdx.x;
+  const int i = b % bx, j = (b / bx) % by, k = b / (bx * by);
+  const double X = i * dx, Y = j * dy, Z = k * dz;
+  if (i >= nx || j >= ny || k >= nz || !oe_near(X, Y, Z, fmax(dx, fmax(dy, dz)))) return;   // whole workgroup
+  __shared__ double part[81];
+  const int t = threadIdx.x;
+  if (t < 81) {
+    const int c = t / 27, p = t % 27;
+    const int di = p % 3 - 1, dj = (p / 3) % 3 - 1, dk = p / 9 - 1;
+    const double w = (di ? 1.0 : -2.0) * (dj ? 1.0 : -2.0) * (dk ? 1.0 : -2.0);
+    const double A = c == 0 ? X : c == 1 ? Y : Z, ha = c == 0 ? dx : c == 1 ? dy : dz;
+    const double B = c == 0 ? Y : X, hb = c == 0 ? dy : dx;
+    const double C = c == 2 ? Y : Z, hc = c == 2 ? dy : dz;
+    part[t] = w * q_path(A + di * ha, B + dj * hb, C + dk * hc, qs, qw, nq);
+  }
+  __syncthreads();
+  if (t < 3) {
+    double acc = 0.0;
+    for (int p = 0; p < 27; ++p) acc += part[t * 27 + p];
+    out[(size_t)t * nx * ny * nz + ((size_t)k * ny + j) * nx + i] = -acc / (dx * dy * dz);
+  }
+}
+
+// Far offsets: the defining integral against the tent weight (the overlap of
+// two cells displaced by u), g = 1/V int prod_a (h_a - |u_a|) (d + u)/|d + u|^3 du,
+// Gauss-Legendre on each half-axis with the tensor's node counts by distance.
+__global__ void k_oe_far(double* __restrict__ out, int nx, int ny, int nz, double dx, double dy, double dz,
+                         GLTable gl) {
+  const size_t cnt = (size_t)nx * ny * nz;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= cnt) return;
+  const int i = (int)(idx % nx);
+  const int j = (int)((idx / nx) % ny);
+  const int k = (int)(idx / ((size_t)nx * ny));
+  const double X = i * dx, Y = j * dy, Z = k * dz;
+  const double hmax = fmax(dx, fmax(dy, dz));
+  if (oe_near(X, Y, Z, hmax)) return;   // written by k_oe_near
+  const double dist = sqrt(X * X + Y * Y + Z * Z) / hmax;
+  const int b = dist < 6.0 ? 0 : dist < 16.0 ? 1 : dist < 40.0 ? 2 : 3;
+  const int n = gl.n[b];
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  for (int ax = 0; ax < 2 * n; ++ax) {
+    const double ux = (ax < n ? 1.0 : -1.0) * gl.u[b][ax % n] * dx;
+    const double wx = gl.w[b][ax % n] * dx * (dx - fabs(ux));
+    const double vx = X + ux;
+    for (int ay = 0; ay < 2 * n; ++ay) {
+      const double uy = (ay < n ? 1.0 : -1.0) * gl.u[b][ay % n] * dy;
+      const double wy = gl.w[b][ay % n] * dy * (dy - fabs(uy));
+      const double vy = Y + uy;
+      for (int az = 0; az < 2 * n; ++az) {
+        const double uz = (az < n ? 1.0 : -1.0) * gl.u[b][az % n] * dz;
+        const double wz = gl.w[b][az % n] * dz * (dz - fabs(uz));
+        const double vz = Z + uz;
+        const double r2 = vx * vx + vy * vy + vz * vz;
+        const double wt = wx * wy * wz / (r2 * sqrt(r2));
+        g0 += wt * vx;
+        g1 += wt * vy;
+        g2 += wt * vz;
+      }
+    }
+  }
+  const double s = 1.0 / (dx * dy * dz);
+  out[idx] = g0 * s;
+  out[cnt + idx] = g1 * s;
+  out[2 * cnt + idx] = g2 * s;
+}
+
 // out[c][o][k][q] = sum_i coef_i * in[c][o][i][q] * trig(i k), 0 <= k < nout,
 // trig = cos (component even along this axis) or sin (odd), coef_0 = 1 and
 // coef_i = 2 for i > 0.  cs holds cos, sn sin of 2 pi m / npad, m < npad.
-__global__ void k_axis(const double* __restrict__ in, double* __restrict__ out, int outer, int nin, int nout,
+__global__ void k_axis(const double* __restrict__ in, double* __restrict__ out, int nc, int outer, int nin, int nout,
                        int inner, int npad, unsigned odd_mask, const double* __restrict__ cs,
                        const double* __restrict__ sn) {
   const size_t per_c = (size_t)outer * nout * inner;
-  const size_t tot = 6 * per_c;
+  const size_t tot = (size_t)nc * per_c;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= tot) return;
   const int c = (int)(idx / per_c);
@@ -167,14 +271,15 @@ __global__ void k_axis(const double* __restrict__ in, double* __restrict__ out, 
   out[idx] = acc;
 }
 
-// in [6][Kzh][Kyh][Kx] (FP64) -> K[kz][kx][c][ky] (FP32, rows of pitch Kyp
+// in [nc][Kzh][Kyh][Kx] (FP64) -> K[kz][kx][c][ky] (FP32, rows of pitch Kyp
 // holding ky < Ny/2, or ky = 0 for Ny = 1, zero padded) and KN[kz][kx][c]
-// (ky = Ny/2, Ny >= 4) after the rows; times -sign_c / npad
-__global__ void k_pack(const double* __restrict__ in, float* __restrict__ K, int Kx, int Kyh, int Kyp, int Kzh,
+// (ky = Ny/2, Ny >= 4) after the rows; times -sign_c / npad (demagnetizing
+// tensor, nc = 6) or 1 / (4 pi npad) (Oersted kernel, nc = 3)
+__global__ void k_pack(const double* __restrict__ in, float* __restrict__ K, int nc, int Kx, int Kyh, int Kyp, int Kzh,
                        int Ny, double inv_npad) {
   const size_t per_c = (size_t)Kzh * Kyh * Kx;
-  const size_t nrow = (size_t)6 * Kzh * Kyp * Kx;
-  const size_t tot = nrow + (size_t)6 * Kzh * Kx;
+  const size_t nrow = (size_t)nc * Kzh * Kyp * Kx;
+  const size_t tot = nrow + (size_t)nc * Kzh * Kx;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= tot) return;
   int ky, c, kx, kz;
@@ -182,21 +287,21 @@ __global__ void k_pack(const double* __restrict__ in, float* __restrict__ K, int
   if (idx < nrow) {
     ky = (int)(idx % Kyp);
     size_t rem = idx / Kyp;
-    c = (int)(rem % 6);
-    rem /= 6;
+    c = (int)(rem % nc);
+    rem /= nc;
     kx = (int)(rem % Kx);
     kz = (int)(rem / Kx);
     have = Ny >= 4 ? ky < Ny / 2 : ky == 0;
   } else {
     size_t rem = idx - nrow;
-    c = (int)(rem % 6);
-    rem /= 6;
+    c = (int)(rem % nc);
+    rem /= nc;
     kx = (int)(rem % Kx);
     kz = (int)(rem / Kx);
     ky = Ny / 2;
     have = Ny >= 4;
   }
-  const double s = (c < 3 ? -1.0 : 1.0) * inv_npad;
+  const double s = nc == 3 ? inv_npad / (4.0 * M_PI) : (c < 3 ? -1.0 : 1.0) * inv_npad;
   K[idx] = have ? (float)(s * in[c * per_c + ((size_t)kz * Kyh + ky) * Kx + kx]) : 0.f;
 }
 
@@ -364,18 +469,36 @@ hipError_t launch_tensor(double* out, const Geom& g, const GLTable& gl, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_axis(const double* in, double* out, int outer, int nin, int nout, int inner, int npad,
+hipError_t launch_axis(const double* in, double* out, int nc, int outer, int nin, int nout, int inner, int npad,
                        unsigned odd_mask, const double* cs, const double* sn, hipStream_t s) {
-  const size_t tot = (size_t)6 * outer * nout * inner;
-  hipLaunchKernelGGL(k_axis, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, in, out, outer, nin, nout, inner,
-                     npad, odd_mask, cs, sn);
+  const size_t tot = (size_t)nc * outer * nout * inner;
+  hipLaunchKernelGGL(k_axis, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, in, out, nc, outer, nin, nout,
+                     inner, npad, odd_mask, cs, sn);
   return hipGetLastError();
 }
 
 hipError_t launch_pack(const double* in, float* K, const Geom& g, hipStream_t s) {
-  const size_t tot = (size_t)6 * g.Kzh * g.Kx * (g.Kyp + 1);
-  hipLaunchKernelGGL(k_pack, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, in, K, g.Kx, g.Kyh, g.Kyp, g.Kzh, g.Ny,
-                     1.0 / ((double)g.Nx * g.Ny * g.Nz));
+  const int nc = kernel_comps(g);
+  const size_t tot = (size_t)nc * g.Kzh * g.Kx * (g.Kyp + 1);
+  hipLaunchKernelGGL(k_pack, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, in, K, nc, g.Kx, g.Kyh, g.Kyp,
+                     g.Kzh, g.Ny, 1.0 / ((double)g.Nx * g.Ny * g.Nz));
+  return hipGetLastError();
+}
+
+hipError_t launch_oe_tensor(double* out, const Geom& g, const GLTable& gl, const double* qs, const double* qw, int nq,
+                            hipStream_t s) {
+  const size_t cnt = (size_t)g.nx * g.ny * g.nz;
+  hipLaunchKernelGGL(k_oe_far, dim3((unsigned)((cnt + 127) / 128)), dim3(128), 0, s, out, g.nx, g.ny, g.nz, g.dx, g.dy,
+                     g.dz, gl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // candidates for |d| < 3 h_max along each axis: index < 3 h_max / h_a
+  const double hmax = std::fmax(g.dx, std::fmax(g.dy, g.dz));
+  const int bx = std::min(g.nx, (int)(3.0 * hmax / g.dx) + 1);
+  const int by = std::min(g.ny, (int)(3.0 * hmax / g.dy) + 1);
+  const int bz = std::min(g.nz, (int)(3.0 * hmax / g.dz) + 1);
+  hipLaunchKernelGGL(k_oe_near, dim3((unsigned)(bx * by * bz)), dim3(128), 0, s, out, g.nx, g.ny, g.nz, g.dx, g.dy,
+                     g.dz, bx, by, qs, qw, nq);
   return hipGetLastError();
 }
 

@@ -25,9 +25,11 @@ int mid_radix(const Geom& g);
 int energy_cell_blocks(size_t ncell);
 
 hipError_t launch_tensor(double* out, const Geom& g, const GLTable& gl, hipStream_t s);
-hipError_t launch_axis(const double* in, double* out, int outer, int nin, int nout, int inner, int npad,
+hipError_t launch_axis(const double* in, double* out, int nc, int outer, int nin, int nout, int inner, int npad,
                        unsigned odd_mask, const double* cs, const double* sn, hipStream_t s);
 hipError_t launch_pack(const double* in, float* K, const Geom& g, hipStream_t s);
+hipError_t launch_oe_tensor(double* out, const Geom& g, const GLTable& gl, const double* qs, const double* qw, int nq,
+                            hipStream_t s);
 hipError_t launch_pair_tensor(double2* out, const PairGeom& pg, const GLTable& gl, hipStream_t s);
 hipError_t launch_fft64(double2* data, int logN, long long es, long long ls, int lpb, long long bstride, int nlines,
                         const double2* tw64, hipStream_t s);

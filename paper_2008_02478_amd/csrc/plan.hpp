@@ -74,8 +74,15 @@ struct Geom {
   int mid_r;           // points per lane of its y line FFT (0: line_radix)
   unsigned pbc;        // periodic axes (bit 0 x, 1 y, 2 z): image-summed tensor
   int images;          // images K on either side along each periodic axis
+  int kind;            // KERNEL_DEMAG or KERNEL_OERSTED
   double dx, dy, dz;
 };
+
+// The convolution kernel of a plan: the demagnetizing tensor (6 real
+// spectrum rows per (kz, kx): xx yy zz xy xz yz) or the Oersted kernel (3
+// rows: the imaginary parts of the Biot-Savart vector's spectrum, x y z).
+enum { KERNEL_DEMAG = 0, KERNEL_OERSTED = 1 };
+inline int kernel_comps(const Geom& g) { return g.kind == KERNEL_OERSTED ? 3 : 6; }
 
 // Work buffer layout: spectrum T[c][kz][tile][y][TILE] (float2), then the
 // FP64 energy partials.

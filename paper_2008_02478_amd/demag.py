@@ -66,6 +66,9 @@ class DemagPlan(_Schedules):
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self._p = ctypes.c_void_p()
         _l.check(self._lib.demag_setup(ctypes.byref(self._p), *self.n, *self.cell, int(pbc), int(images)))
+        self._bind()
+
+    def _bind(self):
         kb, wb = ctypes.c_size_t(), ctypes.c_size_t()
         _l.check(self._lib.demag_buffer_bytes(self._p, ctypes.byref(kb), ctypes.byref(wb)))
         Nx, Ny, Nz = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
@@ -249,6 +252,59 @@ class DemagBatch(_Schedules):
         if p is not None and p.value:
             self._lib.demag_destroy(p)
             self._p = None
+
+
+class OerstedPlan(DemagPlan):
+    """Oersted field of a current density on one mesh of n = (nx, ny, nz)
+    cells of size cell (metres): H = K * J with the cell-averaged Biot-Savart
+    kernel (include/demag.h, demag_setup_oersted).  Open boundaries.  Builds
+    the kernel spectrum on construction; schedules and the tuner as for
+    DemagPlan."""
+
+    def __init__(self, n, cell, device=None):
+        self._lib = _l.load()
+        self.n = tuple(int(v) for v in n)
+        self.cell = tuple(float(v) for v in cell)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self._p = ctypes.c_void_p()
+        _l.check(self._lib.demag_setup_oersted(ctypes.byref(self._p), *self.n, *self.cell))
+        self._bind()
+
+    def field(self, J, scale=1.0, out=None, accumulate=False):
+        """H (A/m) of the current density J (A/m^2, SoA (3, nz, ny, nx)),
+        times scale."""
+        self._check_vec(J, "J")
+        if out is None:
+            out = torch.empty_like(J)
+        else:
+            self._check_vec(out, "out")
+        _l.check(self._lib.demag_oersted_field(self._p, _ptr(J), float(scale), _ptr(out),
+                                               _l.ACCUMULATE if accumulate else 0, _stream()))
+        return out
+
+    def field_2sub(self, *a, **k):
+        raise TypeError("an Oersted plan computes oersted fields only")
+
+    llg_rk4 = energy = backward = field_2sub
+
+
+class OerstedFunction(torch.autograd.Function):
+    """H = K * J with its backward: J -> H is self-adjoint, so the gradient
+    of <G, H> with respect to J is K * G, the same call."""
+
+    @staticmethod
+    def forward(ctx, J, plan, scale):
+        ctx.plan, ctx.scale = plan, scale
+        return plan.field(J.contiguous(), scale)
+
+    @staticmethod
+    def backward(ctx, gH):
+        return ctx.plan.field(gH.contiguous(), ctx.scale), None, None
+
+
+def oersted(J, plan, scale=1.0):
+    """Differentiable Oersted field of the current density J."""
+    return OerstedFunction.apply(J, plan, scale)
 
 
 class DemagFunction(torch.autograd.Function):

@@ -328,3 +328,38 @@ def test_llg_and_two_sublattice_host_checks(lib):
     assert lib.demag_llg_rk4(q, d, ctypes.byref(prm), d, None) == L.EINVAL
     assert lib.demag_field_2sub(q, d, d, 1.0, 1.0, d, 0, None, None) == L.EINVAL
     lib.demag_destroy(q)
+
+
+def test_oersted_plan_host_checks(lib):
+    p = ctypes.c_void_p()
+    assert lib.demag_setup_oersted(None, 8, 8, 1, 1e-9, 1e-9, 1e-9) == L.EINVAL
+    assert lib.demag_setup_oersted(ctypes.byref(p), 0, 8, 1, 1e-9, 1e-9, 1e-9) == L.EINVAL
+    assert lib.demag_setup_oersted(ctypes.byref(p), 8, 8, 1, 1e-9, -1e-9, 1e-9) == L.EINVAL
+    assert lib.demag_setup_oersted(ctypes.byref(p), 8, 8, 65, 1e-9, 1e-9, 1e-9) == L.EUNSUPPORTED
+    assert lib.demag_setup_oersted(ctypes.byref(p), 40, 30, 5, 2e-9, 2e-9, 1e-9) == L.OK
+    kb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.demag_buffer_bytes(p, ctypes.byref(kb), ctypes.byref(wb)) == L.OK
+    rc, q = setup(lib, 40, 30, 5, 2e-9, 2e-9, 1e-9, 0, 0)
+    assert rc == L.OK
+    kq, wq = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.demag_buffer_bytes(q, ctypes.byref(kq), ctypes.byref(wq)) == L.OK
+    # three kernel rows per (kz, kx) instead of six; the same work buffer
+    assert kb.value < kq.value and wb.value == wq.value
+    d = ctypes.c_void_p(256)
+    prm = L.LlgParams(8e5, 1.3e-11, 0.02, 0.0, 1e-13, (ctypes.c_float * 3)(0.0, 0.0, 0.0))
+    nb = ctypes.c_size_t()
+    # the demagnetizing calls refuse an Oersted plan, before the bind state
+    assert lib.demag_field(p, d, None, 1.0, d, 0, None, None) == L.EINVAL
+    assert lib.demag_field_2sub(p, d, d, 1.0, 1.0, d, 0, None, None) == L.EINVAL
+    assert lib.demag_energy(p, d, None, 1.0, d, d, None) == L.EINVAL
+    assert lib.demag_backward(p, d, None, 1.0, None, None, d, 0, None) == L.EINVAL
+    assert lib.demag_llg_workspace_bytes(p, ctypes.byref(nb)) == L.EINVAL
+    assert lib.demag_llg_rk4(p, d, ctypes.byref(prm), d, None) == L.EINVAL
+    # and the Oersted call refuses a demagnetizing plan
+    assert lib.demag_oersted_field(q, d, 1.0, d, 0, None) == L.EINVAL
+    assert lib.demag_oersted_field(None, d, 1.0, d, 0, None) == L.EINVAL
+    assert lib.demag_oersted_field(p, d, 1.0, d, 0, None) == L.ESTATE
+    n = ctypes.c_int()
+    assert lib.demag_schedule_count(p, ctypes.byref(n)) == L.OK and n.value == 1
+    lib.demag_destroy(p)
+    lib.demag_destroy(q)

@@ -1,0 +1,145 @@
+"""GPU parity of the Oersted field (Table 1, Oersted row; Sec. 4): the HIP
+path through the C ABI against the FP64 oracle, H = 1/(4 pi) sum J x g, on
+meshes spanning several tiles with ragged tails, unit axes and long z lines;
+at the full 512 x 512 x 16 size on sampled targets of a compact source
+(whose direct sum the oracle evaluates cell by cell) and self-adjointness
+on random data; every launch schedule;
+the accumulate flag and scale; and the autograd backward (the operator is
+self-adjoint)."""
+import numpy as np
+import pytest
+
+from oracle import oersted as oe
+from paper_2008_02478_amd import inputs
+from tests.gpu_common import TOL, rel_l2, require_gpu, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+J0 = 1e11      # A/m^2
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+CASES = [
+    ((64, 64, 1), (5e-9, 5e-9, 3e-9)),
+    ((40, 30, 5), (2e-9, 2e-9, 1e-9)),
+    ((33, 17, 8), (2e-9, 3e-9, 1e-9)),
+    ((50, 1, 3), (2e-9, 2e-9, 2e-9)),
+    ((1, 24, 6), (1e-9, 2e-9, 1e-9)),
+    ((1, 1, 1), (2e-9, 2e-9, 2e-9)),
+    ((40, 20, 24), (4e-9, 4e-9, 2e-9)),
+    ((24, 16, 40), (3e-9, 3e-9, 1e-9)),
+    ((200, 150, 4), (2e-9, 2e-9, 1e-9)),
+]
+
+
+@pytest.mark.parametrize("n,h", CASES)
+def test_field_matches_oracle(torch, n, h):
+    from paper_2008_02478_amd.demag import OerstedPlan
+    J = (J0 * inputs.gaussian(n, seed=61)).astype(np.float32)
+    say(f"oersted {n} h={h}")
+    Hr = oe.field_fft(J.astype(np.float64), h)
+    plan = OerstedPlan(n, h)
+    H = plan.field(to_dev(J, torch))
+    torch.cuda.synchronize()
+    Hg = H.cpu().numpy()
+    if n == (1, 1, 1):                       # g(0) = 0: a lone cell has no field of its own
+        assert np.max(np.abs(Hg)) <= 1e-6 * J0 * h[0]
+        return
+    err = rel_l2(Hg, Hr)
+    say(f"  rel-L2 {err:.2e}")
+    assert err < TOL
+
+
+def test_accumulate_and_scale(torch):
+    from paper_2008_02478_amd.demag import OerstedPlan
+    n, h = (48, 40, 3), (2e-9, 2e-9, 1e-9)
+    J = (J0 * inputs.gaussian(n, seed=62)).astype(np.float32)
+    base = inputs.gaussian(n, seed=63).astype(np.float32) * 1e3
+    Hr = oe.field_fft(J.astype(np.float64), h)
+    plan = OerstedPlan(n, h)
+    out = to_dev(base, torch)
+    plan.field(to_dev(J, torch), scale=-0.5, out=out, accumulate=True)
+    torch.cuda.synchronize()
+    assert rel_l2(out.cpu().numpy(), base - 0.5 * Hr) < TOL
+
+
+def test_every_schedule(torch):
+    from paper_2008_02478_amd.demag import OerstedPlan
+    n, h = (150, 200, 3), (2e-9, 2e-9, 1e-9)
+    J = (J0 * inputs.gaussian(n, seed=64)).astype(np.float32)
+    Hr = oe.field_fft(J.astype(np.float64), h)
+    plan = OerstedPlan(n, h)
+    Jd = to_dev(J, torch)
+    base = plan.schedules()[0]
+    seen = 0
+    for kw in (2, 4, 8):
+        for r in (4, 8, 16):
+            try:
+                plan.set_schedule(0, kw=kw, radix=r)
+            except Exception:
+                continue
+            H = plan.field(Jd)
+            torch.cuda.synchronize()
+            err = rel_l2(H.cpu().numpy(), Hr)
+            say(f"  kw={kw} radix={r}: {err:.2e}")
+            assert err < TOL
+            seen += 1
+    assert seen >= 3
+    plan.set_schedule(0, yg=base["yg"], kw=base["kw"], radix=base["radix"])
+
+
+def test_autograd_backward_is_the_same_operator(torch):
+    from paper_2008_02478_amd.demag import OerstedPlan, oersted
+    n, h = (36, 28, 4), (2e-9, 2e-9, 1e-9)
+    J = (J0 * inputs.gaussian(n, seed=65)).astype(np.float32)
+    G = inputs.gaussian(n, seed=66).astype(np.float32)
+    plan = OerstedPlan(n, h)
+    Jd = to_dev(J, torch).requires_grad_(True)
+    H = oersted(Jd, plan, 2.0)
+    (H * to_dev(G, torch)).sum().backward()
+    torch.cuda.synchronize()
+    ref = 2.0 * oe.field_fft(G.astype(np.float64), h)     # d<G, 2 K*J>/dJ = 2 K*G
+    assert rel_l2(Jd.grad.cpu().numpy(), ref) < TOL
+
+
+def test_full_size_sampled_targets(torch):
+    """512 x 512 x 16 at 2 x 2 x 1 nm: a random current in an 8 x 8 x 4 box
+    (zero elsewhere); the oracle sums its 256 sources at 24 target cells near
+    and far from the box.  Then self-adjointness of the full-size operator on
+    random data."""
+    from paper_2008_02478_amd.demag import OerstedPlan
+    n, h = (512, 512, 16), (2e-9, 2e-9, 1e-9)
+    nx, ny, nz = n
+    box = (slice(6, 10), slice(300, 308), slice(100, 108))      # z, y, x
+    J = np.zeros((3, nz, ny, nx), np.float32)
+    J[:, box[0], box[1], box[2]] = (J0 * inputs.gaussian((8, 8, 4), seed=67)).astype(np.float32)
+    say("oersted full size 512x512x16")
+    plan = OerstedPlan(n, h)
+    H = plan.field(to_dev(J, torch))
+    torch.cuda.synchronize()
+    Hg = H.cpu().numpy()
+    rng = np.random.default_rng(68)
+    targets = [(7, 303, 104), (0, 300, 100), (15, 310, 111), (8, 296, 98)]
+    targets += [(int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx))) for _ in range(20)]
+    src = np.argwhere(np.any(J != 0, axis=0))
+    Js = J[:, src[:, 0], src[:, 1], src[:, 2]].astype(np.float64)
+    ref = np.zeros((len(targets), 3))
+    for q, (tz, ty, tx) in enumerate(targets):
+        g = oe.g_at((tx - src[:, 2]) * h[0], (ty - src[:, 1]) * h[1], (tz - src[:, 0]) * h[2], h)
+        ref[q] = np.cross(Js.T, g.T).sum(axis=0) / (4 * np.pi)
+    got = np.array([Hg[:, tz, ty, tx] for tz, ty, tx in targets])
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    say(f"  sampled max-abs error / max |H| = {err:.2e}")
+    assert err < TOL
+    # self-adjointness on random data at this size: with C = H[A],
+    # <C, C> = <A, H[C]> (a well-conditioned pair of sums)
+    A = to_dev((J0 * inputs.gaussian(n, seed=69)).astype(np.float32), torch)
+    C = plan.field(A)
+    a = float((C.double() ** 2).sum())
+    b = float((A.double() * plan.field(C).double()).sum())
+    say(f"  <C, C> = {a:.6e}, <A, H[C]> = {b:.6e}")
+    assert abs(a - b) <= TOL * abs(a)
