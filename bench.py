@@ -153,6 +153,65 @@ def bench_llg(torch, plan, m_np, steps=10):
             "params": {k: (list(v) if isinstance(v, tuple) else v) for k, v in kw.items()}}
 
 
+def oersted_mid_bytes(n):
+    """Algorithmic HBM bytes of one Oersted middle-pass launch: the spectrum
+    read and written as for the demagnetizing field, and 3 kernel rows
+    (instead of 6) per (kz, kx) of the octant."""
+    from oracle.conv import padded_len  # plain arithmetic on sizes
+    nx, ny, nz = n
+    Nx, Ny, Nz = padded_len(nx), padded_len(ny), padded_len(nz)
+    Kx = Nx // 2 + 1 if Nx > 1 else 1
+    Ky = Ny // 2 + 1 if Ny > 1 else 1
+    Kz = Nz // 2 + 1 if Nz > 1 else 1
+    return 2 * 3 * Nz * Kx * ny * 8 + 3 * Kz * Ky * Kx * 4
+
+
+def bench_oersted(torch, n, h, seed, steps=30, tune=True, cache=None):
+    """Oersted field H = K * J of a random current density on the benchmark
+    mesh: time per evaluation, per pass, and the middle pass against HBM."""
+    import ctypes
+    from paper_2008_02478_amd import inputs, lib
+    from paper_2008_02478_amd.demag import OerstedPlan
+    L = lib.load()
+    t0 = time.time()
+    plan = OerstedPlan(n, h)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    if tune:
+        plan.autotune(cache=cache)
+    J = torch.from_numpy((1e11 * inputs.gaussian(n, seed=seed)).astype(np.float32)).to(plan.device)
+    H = torch.empty_like(J)
+    for _ in range(5):
+        plan.field(J, out=H)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    for s in evs:           # a torch event has a HIP event only once recorded
+        for e in s:
+            e.record()
+    torch.cuda.synchronize()
+    handles = [(ctypes.c_void_p * 4)(*[e.cuda_event for e in s]) for s in evs]
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for k in range(steps):
+        lib.check(L.demag_set_timing_events(plan._p, handles[k], 4))
+        plan.field(J, out=H)
+    b.record()
+    torch.cuda.synchronize()
+    lib.check(L.demag_set_timing_events(plan._p, None, 0))
+    ms = a.elapsed_time(b) / steps
+    pass_us = {"fwd_xz": 1e3 * float(np.mean([s[0].elapsed_time(s[1]) for s in evs])),
+               "mid_y": 1e3 * float(np.mean([s[1].elapsed_time(s[2]) for s in evs])),
+               "inv_zx": 1e3 * float(np.mean([s[2].elapsed_time(s[3]) for s in evs]))}
+    mb = oersted_mid_bytes(n)
+    ach = mb / (pass_us["mid_y"] * 1e-6) / 1e9
+    return {"workload": f"Oersted field of a random current density on the {n[0]}x{n[1]}x{n[2]} mesh "
+                        "(cell-averaged Biot-Savart kernel, open boundaries)",
+            "ms_per_eval": ms, "cell_updates_per_s": n[0] * n[1] * n[2] / (ms * 1e-3), "pass_us": pass_us,
+            "setup_s": setup_s, "schedule": plan.schedules()[0],
+            "mid_roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": mb}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,6 +361,7 @@ def main():
 
     out["batched_multi_mesh"] = bench_batch(torch, tune=not args.no_tune, cache=args.schedule_cache)
     out["llg_rk4"] = bench_llg(torch, plan, m_np)
+    out["oersted"] = bench_oersted(torch, n, h, wl["seed"] + 200, tune=not args.no_tune, cache=args.schedule_cache)
 
     if not args.no_cpu_baseline:
         from oracle import conv
