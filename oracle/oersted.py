@@ -141,18 +141,28 @@ def g_at(X, Y, Z, h):
     return out
 
 
-def g_octant(n, h):
-    """g at the non-negative lattice offsets; [3, nz, ny, nx]."""
+def g_octant(n, h, pbc=(False, False, False), images=0):
+    """g at the non-negative lattice offsets; [3, nz, ny, nx].  With periodic
+    axes (multiple images, Sec. 3, the reading taken for the demagnetizing
+    tensor): the sum of g over the shifts k o L, |k_a| <= images on the
+    periodic axes, L_a = n_a h_a, i.e. the field of the (2K+1)-times repeated
+    mesh read in its central copy.  The image set is symmetric, so the sum
+    keeps g's parities."""
+    from .pbc import image_shifts
     nx, ny, nz = n
     k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    return g_at(i * h[0], j * h[1], k * h[2], h)
+    X, Y, Z = i * h[0], j * h[1], k * h[2]
+    out = np.zeros((3, nz, ny, nx))
+    for sx, sy, sz in image_shifts(n, h, pbc, images if any(pbc) else 0):
+        out += g_at(X + sx, Y + sy, Z + sz, h)
+    return out
 
 
-def g_full(n, h):
+def g_full(n, h, pbc=(False, False, False), images=0):
     """g at every lattice offset -(n_a - 1) .. (n_a - 1) from the octant and
     the parities; [3, 2nz-1, 2ny-1, 2nx-1], zero offset at (nz-1, ny-1, nx-1)."""
     nx, ny, nz = n
-    octn = g_octant(n, h)
+    octn = g_octant(n, h, pbc, images)
     idx = [np.arange(-(m - 1), m) for m in (nx, ny, nz)]
     full = np.zeros((3, 2 * nz - 1, 2 * ny - 1, 2 * nx - 1))
     for c in range(3):

@@ -151,3 +151,40 @@ def test_self_adjoint():
     a = float(np.sum(G * oe.field_fft(J, h)))
     b = float(np.sum(J * oe.field_fft(G, h)))
     assert abs(a - b) <= 1e-12 * (abs(a) + abs(b))
+
+
+@pytest.mark.parametrize("n,h,pbc,K", [
+    ((5, 4, 2), (2e-9, 3e-9, 1e-9), (True, False, False), 2),
+    ((4, 3, 2), (2e-9, 2e-9, 1e-9), (True, True, False), 1),
+    ((4, 3, 2), (5e-9, 5e-9, 3e-9), (False, False, True), 2),
+    ((3, 3, 2), (2e-9, 2e-9, 2e-9), (True, True, True), 1),
+])
+def test_periodic_images_equal_repeated_mesh(n, h, pbc, K):
+    """Multiple images (Sec. 3): the image-summed kernel gives exactly the
+    open-boundary field of the (2K+1)-times repeated mesh in its central copy."""
+    J = inputs.gaussian(n, seed=94)
+    Hp = oe.field_direct(J, h, oe.g_full(n, h, pbc, K))
+    reps = [2 * K + 1 if p else 1 for p in pbc]
+    big = tuple(n[a] * reps[a] for a in range(3))
+    Hbig = oe.field_direct(np.tile(J, (1, reps[2], reps[1], reps[0])), h, oe.g_full(big, h))
+    c = [K * n[a] if pbc[a] else 0 for a in range(3)]
+    Hc = Hbig[:, c[2]:c[2] + n[2], c[1]:c[1] + n[1], c[0]:c[0] + n[0]]
+    assert np.linalg.norm(Hp - Hc) <= 1e-12 * np.linalg.norm(Hc)
+    assert np.linalg.norm(oe.field_fft(J, h, oe.g_full(n, h, pbc, K)) - Hp) <= 1e-12 * np.linalg.norm(Hp)
+
+
+def test_periodic_film_tends_to_current_sheet():
+    """A film of two layers periodic in x and y carrying a uniform current
+    density J along x is an infinite slab: by Ampere's law H_y = -J z inside
+    (z from the mid-plane), so the layers average -+J dz/2, and H_x = H_z = 0.
+    The image sum approaches this as K grows."""
+    n, h, J0 = (4, 4, 2), (2e-9, 2e-9, 1e-9), 1e11
+    J = np.zeros((3, 2, 4, 4))
+    J[0] = J0
+    errs = []
+    for K in (5, 20):
+        H = oe.field_direct(J, h, oe.g_full(n, h, (True, True, False), K))
+        expect = np.array([J0 * h[2] / 2, -J0 * h[2] / 2])[:, None, None]
+        assert np.max(np.abs(H[0])) < 1e-9 * J0 * h[2]
+        errs.append(max(np.max(np.abs(H[1] - expect)), np.max(np.abs(H[2]))) / (J0 * h[2] / 2))
+    assert errs[0] < 0.1 and errs[1] < 0.03 and errs[1] < errs[0] / 3
