@@ -221,6 +221,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch schedules")
     ap.add_argument("--schedule-cache", default=None, help="JSON schedule cache to apply (and extend)")
+    ap.add_argument("--main-only", action="store_true",
+                    help="time the field + backward step only (no batch, RK4 or Oersted legs), e.g. under a profiler")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
@@ -359,9 +361,11 @@ def main():
         },
     }
 
-    out["batched_multi_mesh"] = bench_batch(torch, tune=not args.no_tune, cache=args.schedule_cache)
-    out["llg_rk4"] = bench_llg(torch, plan, m_np)
-    out["oersted"] = bench_oersted(torch, n, h, wl["seed"] + 200, tune=not args.no_tune, cache=args.schedule_cache)
+    if not args.main_only:
+        out["batched_multi_mesh"] = bench_batch(torch, tune=not args.no_tune, cache=args.schedule_cache)
+        out["llg_rk4"] = bench_llg(torch, plan, m_np)
+        out["oersted"] = bench_oersted(torch, n, h, wl["seed"] + 200, tune=not args.no_tune,
+                                       cache=args.schedule_cache)
 
     if not args.no_cpu_baseline:
         from oracle import conv

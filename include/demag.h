@@ -201,10 +201,12 @@ int demag_llg_rk4(const demag_plan* plan, float* d_m, const demag_llg_params* pa
  * near the source, Gauss-Legendre quadrature of the defining integral
  * beyond).  The field passes are those of demag_field with this kernel's
  * product, H^ = i (P x J^) per frequency.  J is SoA [3][nz][ny][nx] FP32 in
- * A/m^2 (scale = 1) and H is in A/m; open boundaries only.
+ * A/m^2 (scale = 1) and H is in A/m.
  *
- * demag_setup_oersted: as demag_setup, same size limits, no periodic axes;
- * bind with demag_buffer_bytes / demag_bind as any plan.  An Oersted plan is
+ * demag_setup_oersted: as demag_setup, same size limits and periodic axes
+ * (the kernel summed over pbc_images images on either side, the field of the
+ * repeated mesh in its central copy); bind with demag_buffer_bytes /
+ * demag_bind as any plan.  An Oersted plan is
  * refused (DEMAG_EINVAL) by demag_field, _2sub, _energy, _backward and the
  * LLG calls; schedules and the tuner apply as for a demagnetizing plan.
  *
@@ -214,7 +216,8 @@ int demag_llg_rk4(const demag_plan* plan, float* d_m, const demag_llg_params* pa
  * d<G, H[J]>/dJ = scale K*G.  DEMAG_EINVAL for NULL buffers, unknown flags,
  * a non-finite scale or a plan that is not an Oersted plan; DEMAG_ESTATE
  * before demag_bind. */
-int demag_setup_oersted(demag_plan** out, int nx, int ny, int nz, double dx, double dy, double dz);
+int demag_setup_oersted(demag_plan** out, int nx, int ny, int nz, double dx, double dy, double dz,
+                        unsigned pbc_flags, int pbc_images);
 int demag_oersted_field(const demag_plan* plan, const float* d_J, float scale, float* d_H, unsigned flags,
                         void* stream);
 

@@ -790,11 +790,15 @@ int demag_setup(demag_plan** out, int nx, int ny, int nz, double dx, double dy, 
   return DEMAG_OK;
 }
 
-int demag_setup_oersted(demag_plan** out, int nx, int ny, int nz, double dx, double dy, double dz) {
+int demag_setup_oersted(demag_plan** out, int nx, int ny, int nz, double dx, double dy, double dz, unsigned pbc_flags,
+                        int pbc_images) {
   if (!out) return fail(DEMAG_EINVAL, "demag_setup_oersted: out is NULL");
   *out = nullptr;
   Geom g;
-  int rc = make_geom(nx, ny, nz, dx, dy, dz, 0u, 0, g, "demag_setup_oersted");
+  if (pbc_flags & ~7u) return fail(DEMAG_EINVAL, "demag_setup_oersted: unknown boundary flags");
+  if (pbc_flags && pbc_images > MAX_IMAGES)
+    return fail(DEMAG_EINVAL, "demag_setup_oersted: at most 1000 images per side");
+  int rc = make_geom(nx, ny, nz, dx, dy, dz, pbc_flags, pbc_images, g, "demag_setup_oersted");
   if (rc != DEMAG_OK) return rc;
   g.kind = KERNEL_OERSTED;
   demag_plan* p = new (std::nothrow) demag_plan;

@@ -19,7 +19,8 @@
 // The Oersted kernel (Table 1, Oersted row; Sec. 4) takes the same route with
 // three components: g(d), the field of a cuboid cell of unit current density
 // averaged over the target cell at offset d (H = 1/(4 pi) J x g), built by
-// k_oe_near (|d| < 3 h_max) and k_oe_far; g_a is odd along axis a only, so
+// k_oe_far (then, with periodic axes, summed over the images like the
+// tensor) and k_oe_near (|d| < 3 h_max); g_a is odd along axis a only, so
 // its spectrum is -i times a real octant, packed as 1/(4 pi Nx Ny Nz) times
 // that real part.
 #include <hip/hip_runtime.h>
@@ -166,12 +167,33 @@ __device__ double q_path(double X, double Y, double Z, const double* __restrict_
   return (X < 0.0 ? -ax : ax) * acc;
 }
 
-// Near offsets (|d| < 3 h_max), one workgroup each over the box bx x by x bz
-// of candidates: (r - r')_a / |r - r'|^3 = d/dr'_a (1/|r - r'|), so
+// weight of stencil point p (0..26) and its offsets along the three axes
+__device__ __forceinline__ double oe_stencil(int p, int& di, int& dj, int& dk) {
+  di = p % 3 - 1;
+  dj = (p / 3) % 3 - 1;
+  dk = p / 9 - 1;
+  return (di ? 1.0 : -2.0) * (dj ? 1.0 : -2.0) * (dk ? 1.0 : -2.0);
+}
+
+// term p of component c at offset (X, Y, Z): (A, B, C) is the offset taken
+// along (c, then the other two axes), f being symmetric in its last two
+__device__ double oe_term(int c, int p, double X, double Y, double Z, double dx, double dy, double dz,
+                          const double* __restrict__ qs, const double* __restrict__ qw, int nq) {
+  int di, dj, dk;
+  const double w = oe_stencil(p, di, dj, dk);
+  const double A = c == 0 ? X : c == 1 ? Y : Z, ha = c == 0 ? dx : c == 1 ? dy : dz;
+  const double B = c == 0 ? Y : X, hb = c == 0 ? dy : dx;
+  const double C = c == 2 ? Y : Z, hc = c == 2 ? dy : dz;
+  return w * q_path(A + di * ha, B + dj * hb, C + dk * hc, qs, qw, nq);
+}
+
+// Near offsets (|d| < 3 h_max) of the central image, one workgroup each over
+// the box bx x by x bz of candidates:
+// (r - r')_a / |r - r'|^3 = d/dr'_a (1/|r - r'|), so
 //   g_a = -(1/V) sum_{i,j,k} w_i w_j w_k Q(A + i h_a, B + j h_b, C + k h_c),
-// w_0 = -2, w_{+-1} = 1, with (A, B, C) the offset taken along (a, b, c), b
-// and c the other two axes.  81 lanes take one (component, stencil point)
-// each; lane c sums its component's 27 terms in a fixed order.
+// w_0 = -2, w_{+-1} = 1.  81 lanes take one (component, stencil point)
+// each; lane c sums its component's 27 terms in a fixed order and adds the
+// result to what k_oe_far left there (the other images' sum, or 0).
 __global__ void __launch_bounds__(128) k_oe_near(double* __restrict__ out, int nx, int ny, int nz, double dx,
                                                  double dy, double dz, int bx, int by, const double* __restrict__ qs,
                                                  const double* __restrict__ qw, int nq) {
@@ -181,65 +203,86 @@ __global__ void __launch_bounds__(128) k_oe_near(double* __restrict__ out, int n
   if (i >= nx || j >= ny || k >= nz || !oe_near(X, Y, Z, fmax(dx, fmax(dy, dz)))) return;   // whole workgroup
   __shared__ double part[81];
   const int t = threadIdx.x;
-  if (t < 81) {
-    const int c = t / 27, p = t % 27;
-    const int di = p % 3 - 1, dj = (p / 3) % 3 - 1, dk = p / 9 - 1;
-    const double w = (di ? 1.0 : -2.0) * (dj ? 1.0 : -2.0) * (dk ? 1.0 : -2.0);
-    const double A = c == 0 ? X : c == 1 ? Y : Z, ha = c == 0 ? dx : c == 1 ? dy : dz;
-    const double B = c == 0 ? Y : X, hb = c == 0 ? dy : dx;
-    const double C = c == 2 ? Y : Z, hc = c == 2 ? dy : dz;
-    part[t] = w * q_path(A + di * ha, B + dj * hb, C + dk * hc, qs, qw, nq);
-  }
+  if (t < 81) part[t] = oe_term(t / 27, t % 27, X, Y, Z, dx, dy, dz, qs, qw, nq);
   __syncthreads();
   if (t < 3) {
     double acc = 0.0;
     for (int p = 0; p < 27; ++p) acc += part[t * 27 + p];
-    out[(size_t)t * nx * ny * nz + ((size_t)k * ny + j) * nx + i] = -acc / (dx * dy * dz);
+    out[(size_t)t * nx * ny * nz + ((size_t)k * ny + j) * nx + i] += -acc / (dx * dy * dz);
   }
 }
 
-// Far offsets: the defining integral against the tent weight (the overlap of
-// two cells displaced by u), g = 1/V int prod_a (h_a - |u_a|) (d + u)/|d + u|^3 du,
-// Gauss-Legendre on each half-axis with the tensor's node counts by distance.
-__global__ void k_oe_far(double* __restrict__ out, int nx, int ny, int nz, double dx, double dy, double dz,
-                         GLTable gl) {
+// Far offsets, and with periodic axes the sum over the images
+// d + (a Lx, b Ly, c Lz), |a| <= Kx, ...: far images by the defining integral
+// against the tent weight (the overlap of two cells displaced by u),
+//   g = 1/V int prod_a (h_a - |u_a|) (d + u)/|d + u|^3 du,
+// Gauss-Legendre on each half-axis with the tensor's node counts by distance;
+// near images other than the central one by the path-integral reduction in
+// this thread (only short periods have any).  The central image's near
+// offsets are left at 0 for k_oe_near.
+__global__ void __launch_bounds__(128) k_oe_far(double* __restrict__ out, int nx, int ny, int nz, double dx,
+                                                double dy, double dz, GLTable gl, int Kx, int Ky, int Kz,
+                                                const double* __restrict__ qs, const double* __restrict__ qw,
+                                                int nq) {
   const size_t cnt = (size_t)nx * ny * nz;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= cnt) return;
   const int i = (int)(idx % nx);
   const int j = (int)((idx / nx) % ny);
   const int k = (int)(idx / ((size_t)nx * ny));
-  const double X = i * dx, Y = j * dy, Z = k * dz;
   const double hmax = fmax(dx, fmax(dy, dz));
-  if (oe_near(X, Y, Z, hmax)) return;   // written by k_oe_near
-  const double dist = sqrt(X * X + Y * Y + Z * Z) / hmax;
-  const int b = dist < 6.0 ? 0 : dist < 16.0 ? 1 : dist < 40.0 ? 2 : 3;
-  const int n = gl.n[b];
+  const double Lx = nx * dx, Ly = ny * dy, Lz = nz * dz;
   double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-  for (int ax = 0; ax < 2 * n; ++ax) {
-    const double ux = (ax < n ? 1.0 : -1.0) * gl.u[b][ax % n] * dx;
-    const double wx = gl.w[b][ax % n] * dx * (dx - fabs(ux));
-    const double vx = X + ux;
-    for (int ay = 0; ay < 2 * n; ++ay) {
-      const double uy = (ay < n ? 1.0 : -1.0) * gl.u[b][ay % n] * dy;
-      const double wy = gl.w[b][ay % n] * dy * (dy - fabs(uy));
-      const double vy = Y + uy;
-      for (int az = 0; az < 2 * n; ++az) {
-        const double uz = (az < n ? 1.0 : -1.0) * gl.u[b][az % n] * dz;
-        const double wz = gl.w[b][az % n] * dz * (dz - fabs(uz));
-        const double vz = Z + uz;
-        const double r2 = vx * vx + vy * vy + vz * vz;
-        const double wt = wx * wy * wz / (r2 * sqrt(r2));
-        g0 += wt * vx;
-        g1 += wt * vy;
-        g2 += wt * vz;
+  for (int ia = -Kx; ia <= Kx; ++ia)
+    for (int ib = -Ky; ib <= Ky; ++ib)
+      for (int ic = -Kz; ic <= Kz; ++ic) {
+        const double X = i * dx + ia * Lx, Y = j * dy + ib * Ly, Z = k * dz + ic * Lz;
+        if (oe_near(X, Y, Z, hmax)) {
+          if (ia == 0 && ib == 0 && ic == 0) continue;   // k_oe_near
+          double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+          for (int p = 0; p < 27; ++p) {
+            a0 += oe_term(0, p, X, Y, Z, dx, dy, dz, qs, qw, nq);
+            a1 += oe_term(1, p, X, Y, Z, dx, dy, dz, qs, qw, nq);
+            a2 += oe_term(2, p, X, Y, Z, dx, dy, dz, qs, qw, nq);
+          }
+          const double s = -1.0 / (dx * dy * dz);
+          g0 += s * a0;
+          g1 += s * a1;
+          g2 += s * a2;
+          continue;
+        }
+        const double dist = sqrt(X * X + Y * Y + Z * Z) / hmax;
+        const int b = dist < 6.0 ? 0 : dist < 16.0 ? 1 : dist < 40.0 ? 2 : 3;
+        const int n = gl.n[b];
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int ax = 0; ax < 2 * n; ++ax) {
+          const double ux = (ax < n ? 1.0 : -1.0) * gl.u[b][ax % n] * dx;
+          const double wx = gl.w[b][ax % n] * dx * (dx - fabs(ux));
+          const double vx = X + ux;
+          for (int ay = 0; ay < 2 * n; ++ay) {
+            const double uy = (ay < n ? 1.0 : -1.0) * gl.u[b][ay % n] * dy;
+            const double wy = gl.w[b][ay % n] * dy * (dy - fabs(uy));
+            const double vy = Y + uy;
+            for (int az = 0; az < 2 * n; ++az) {
+              const double uz = (az < n ? 1.0 : -1.0) * gl.u[b][az % n] * dz;
+              const double wz = gl.w[b][az % n] * dz * (dz - fabs(uz));
+              const double vz = Z + uz;
+              const double r2 = vx * vx + vy * vy + vz * vz;
+              const double wt = wx * wy * wz / (r2 * sqrt(r2));
+              s0 += wt * vx;
+              s1 += wt * vy;
+              s2 += wt * vz;
+            }
+          }
+        }
+        const double s = 1.0 / (dx * dy * dz);
+        g0 += s * s0;
+        g1 += s * s1;
+        g2 += s * s2;
       }
-    }
-  }
-  const double s = 1.0 / (dx * dy * dz);
-  out[idx] = g0 * s;
-  out[cnt + idx] = g1 * s;
-  out[2 * cnt + idx] = g2 * s;
+  out[idx] = g0;
+  out[cnt + idx] = g1;
+  out[2 * cnt + idx] = g2;
 }
 
 // out[c][o][k][q] = sum_i coef_i * in[c][o][i][q] * trig(i k), 0 <= k < nout,
@@ -488,8 +531,9 @@ hipError_t launch_pack(const double* in, float* K, const Geom& g, hipStream_t s)
 hipError_t launch_oe_tensor(double* out, const Geom& g, const GLTable& gl, const double* qs, const double* qw, int nq,
                             hipStream_t s) {
   const size_t cnt = (size_t)g.nx * g.ny * g.nz;
+  const int K = g.images;
   hipLaunchKernelGGL(k_oe_far, dim3((unsigned)((cnt + 127) / 128)), dim3(128), 0, s, out, g.nx, g.ny, g.nz, g.dx, g.dy,
-                     g.dz, gl);
+                     g.dz, gl, (g.pbc & 1u) ? K : 0, (g.pbc & 2u) ? K : 0, (g.pbc & 4u) ? K : 0, qs, qw, nq);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // candidates for |d| < 3 h_max along each axis: index < 3 h_max / h_a

@@ -257,17 +257,17 @@ class DemagBatch(_Schedules):
 class OerstedPlan(DemagPlan):
     """Oersted field of a current density on one mesh of n = (nx, ny, nz)
     cells of size cell (metres): H = K * J with the cell-averaged Biot-Savart
-    kernel (include/demag.h, demag_setup_oersted).  Open boundaries.  Builds
-    the kernel spectrum on construction; schedules and the tuner as for
-    DemagPlan."""
+    kernel (include/demag.h, demag_setup_oersted).  pbc / images as for
+    DemagPlan.  Builds the kernel spectrum on construction; schedules and the
+    tuner as for DemagPlan."""
 
-    def __init__(self, n, cell, device=None):
+    def __init__(self, n, cell, device=None, pbc=0, images=0):
         self._lib = _l.load()
         self.n = tuple(int(v) for v in n)
         self.cell = tuple(float(v) for v in cell)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self._p = ctypes.c_void_p()
-        _l.check(self._lib.demag_setup_oersted(ctypes.byref(self._p), *self.n, *self.cell))
+        _l.check(self._lib.demag_setup_oersted(ctypes.byref(self._p), *self.n, *self.cell, int(pbc), int(images)))
         self._bind()
 
     def field(self, J, scale=1.0, out=None, accumulate=False):

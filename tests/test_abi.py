@@ -332,11 +332,15 @@ def test_llg_and_two_sublattice_host_checks(lib):
 
 def test_oersted_plan_host_checks(lib):
     p = ctypes.c_void_p()
-    assert lib.demag_setup_oersted(None, 8, 8, 1, 1e-9, 1e-9, 1e-9) == L.EINVAL
-    assert lib.demag_setup_oersted(ctypes.byref(p), 0, 8, 1, 1e-9, 1e-9, 1e-9) == L.EINVAL
-    assert lib.demag_setup_oersted(ctypes.byref(p), 8, 8, 1, 1e-9, -1e-9, 1e-9) == L.EINVAL
-    assert lib.demag_setup_oersted(ctypes.byref(p), 8, 8, 65, 1e-9, 1e-9, 1e-9) == L.EUNSUPPORTED
-    assert lib.demag_setup_oersted(ctypes.byref(p), 40, 30, 5, 2e-9, 2e-9, 1e-9) == L.OK
+    assert lib.demag_setup_oersted(None, 8, 8, 1, 1e-9, 1e-9, 1e-9, 0, 0) == L.EINVAL
+    assert lib.demag_setup_oersted(ctypes.byref(p), 0, 8, 1, 1e-9, 1e-9, 1e-9, 0, 0) == L.EINVAL
+    assert lib.demag_setup_oersted(ctypes.byref(p), 8, 8, 1, 1e-9, -1e-9, 1e-9, 0, 0) == L.EINVAL
+    assert lib.demag_setup_oersted(ctypes.byref(p), 8, 8, 65, 1e-9, 1e-9, 1e-9, 0, 0) == L.EUNSUPPORTED
+    assert lib.demag_setup_oersted(ctypes.byref(p), 8, 8, 1, 1e-9, 1e-9, 1e-9, 8, 0) == L.EINVAL
+    assert lib.demag_setup_oersted(ctypes.byref(p), 8, 8, 1, 1e-9, 1e-9, 1e-9, L.PBC_X, 1001) == L.EINVAL
+    assert lib.demag_setup_oersted(ctypes.byref(p), 8, 8, 1, 1e-9, 1e-9, 1e-9, L.PBC_X | L.PBC_Y, 0) == L.OK
+    lib.demag_destroy(p)
+    assert lib.demag_setup_oersted(ctypes.byref(p), 40, 30, 5, 2e-9, 2e-9, 1e-9, 0, 0) == L.OK
     kb, wb = ctypes.c_size_t(), ctypes.c_size_t()
     assert lib.demag_buffer_bytes(p, ctypes.byref(kb), ctypes.byref(wb)) == L.OK
     rc, q = setup(lib, 40, 30, 5, 2e-9, 2e-9, 1e-9, 0, 0)
