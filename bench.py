@@ -29,6 +29,9 @@ HBM_PEAK_GBS = 8000.0
 # instruction per clock (four SIMDs, 16 lanes, 4 cycles per instruction) at
 # 2.4 GHz; packed FP32 is not used.
 VALU_INSTS_PER_S = 256 * 2.4e9
+# FP32 vector peak without packed FP32: 256 CUs x 64 lanes x 2 (fused
+# multiply-add) x 2.4 GHz
+FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 WORKLOADS = {
     "512x512x16": dict(n=(512, 512, 16), h=(2e-9, 2e-9, 1e-9), Ms=1.1e6, seed=10),
     "1024x1024x4": dict(n=(1024, 1024, 4), h=(2e-9, 2e-9, 1e-9), Ms=1.1e6, seed=11),
@@ -51,6 +54,23 @@ def mid_pass_bytes(n):
     Kz = Nz // 2 + 1 if Nz > 1 else 1
     spec = 3 * Nz * Kx * ny * 8
     return 2 * spec + 6 * Kz * Ky * Kx * 4
+
+
+def mid_pass_flops(n):
+    """Algorithmic FP32 operations of one middle-pass launch, counting a
+    complex M-point FFT as 5 M log2 M: per (kz, kx) line and component the two
+    residue FFTs forward and inverse (M = Ny/2), the odd residue's twiddle each
+    way (6 per point) and the residue sum (2 per point); per frequency the
+    3x3 real-by-complex product (30)."""
+    import math
+    from oracle.conv import padded_len  # plain arithmetic on sizes
+    nx, ny, nz = n
+    Nx, Ny, Nz = padded_len(nx), padded_len(ny), padded_len(nz)
+    Kx = Nx // 2 + 1 if Nx > 1 else 1
+    M = Ny // 2 if Ny > 1 else 1
+    fft = 5 * M * math.log2(M) if M > 1 else 0
+    per_line = 3 * (4 * fft + 12 * M + 2 * M) + 30 * Ny
+    return per_line * Nz * Kx
 
 
 def bench_batch(torch, reps=10, tune=True, cache=None):
@@ -358,6 +378,10 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": mid_bytes,
             "valu": valu,
+            "alu": {"algorithmic_flop_per_launch": mid_pass_flops(n),
+                    "achieved_tflops": mid_pass_flops(n) / (pass_us["mid_y"] * 1e-6) / 1e12,
+                    "peak_tflops": FP32_PEAK_TFLOPS,
+                    "frac": mid_pass_flops(n) / (pass_us["mid_y"] * 1e-6) / 1e12 / FP32_PEAK_TFLOPS},
         },
     }
 
