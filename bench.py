@@ -235,7 +235,7 @@ def bench_oersted(torch, n, h, seed, steps=30, tune=True, cache=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=1300)   # about 1 s of timed field + backward steps
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="512x512x16", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
