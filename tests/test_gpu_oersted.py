@@ -201,3 +201,24 @@ def test_graph_capture_replays(torch):
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(H, H0), f"replay {k}"
+
+
+def test_autotune_cache_key_and_parity(torch, tmp_path):
+    """The tuner measures an Oersted plan under its own cache key (its middle
+    pass differs from a demagnetizing plan's of the same mesh) and the tuned
+    schedule still matches the oracle."""
+    import json
+    from paper_2008_02478_amd.demag import DemagPlan, OerstedPlan
+    n, h = (150, 200, 3), (2e-9, 2e-9, 1e-9)
+    cache = tmp_path / "sched.json"
+    assert DemagPlan(n, h).autotune(cache=cache) == 1
+    p = OerstedPlan(n, h)
+    assert p.autotune(cache=cache) == 1              # not served by the demagnetizing entry
+    keys = sorted(json.loads(cache.read_text())["entries"])
+    say(f"  cache keys {keys}")
+    assert any("|oersted 150x200x3 nb=1" in k for k in keys) and any("|mesh 150x200x3 nb=1" in k for k in keys)
+    assert OerstedPlan(n, h).autotune(cache=cache) == 0
+    J = (J0 * inputs.gaussian(n, seed=73)).astype(np.float32)
+    H = p.field(to_dev(J, torch))
+    torch.cuda.synchronize()
+    assert rel_l2(H.cpu().numpy(), oe.field_fft(J.astype(np.float64), h)) < TOL
