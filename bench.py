@@ -73,6 +73,54 @@ def mid_pass_flops(n):
     return per_line * Nz * Kx
 
 
+def path_bytes(n):
+    """Per field evaluation: (algorithmic, compulsory) HBM bytes.  Algorithmic:
+    the three passes' reads and writes (M in, spectrum out; spectrum in and
+    out plus the kernel octant; spectrum in, H out).  Compulsory: read M and the
+    kernel octant once, write H."""
+    from oracle.conv import padded_len  # plain arithmetic on sizes
+    nx, ny, nz = n
+    Nx, Ny, Nz = padded_len(nx), padded_len(ny), padded_len(nz)
+    Kx = Nx // 2 + 1 if Nx > 1 else 1
+    Ky = Ny // 2 + 1 if Ny > 1 else 1
+    Kz = Nz // 2 + 1 if Nz > 1 else 1
+    vec = 3 * nx * ny * nz * 4
+    spec = 3 * Nz * Kx * ny * 8
+    kern = 6 * Kz * Ky * Kx * 4
+    return 2 * vec + 4 * spec + kern, 2 * vec + kern
+
+
+def bench_copy(torch, mib=1024, reps=10):
+    """Read + write rate (GB/s) of the library's plain streaming copy, and of
+    torch's copy for reference, over 1 GiB buffers."""
+    import ctypes
+    from paper_2008_02478_amd import lib
+    L = lib.load()
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    call = lambda: lib.check(L.demag_stream_copy(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                                 x.numel() * 4, st))
+    call()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        call()
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2 * x.numel() * 4 * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    torch_gbs = 2 * x.numel() * 4 * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del x, y
+    return gbs, torch_gbs
+
+
 def bench_batch(torch, reps=10, tune=True, cache=None):
     """Batched multi-mesh workload: three coupled layers (512x512x2 and
     512x512x1 of 1 nm cells, 256x256x3 of 2 nm cells, 1 nm and 3 nm
@@ -385,6 +433,15 @@ def main():
         },
     }
 
+    alg, comp = path_bytes(n)
+    copy_gbs, torch_copy_gbs = bench_copy(torch)
+    step_gbs = 2 * alg / (ms_step * 1e-3) / 1e9
+    out["path"] = {
+        "algorithmic_bytes_per_eval": alg, "compulsory_bytes_per_eval": comp,
+        "achieved_gbs": step_gbs, "frac_of_peak": step_gbs / HBM_PEAK_GBS,
+        "copy_gbs": copy_gbs, "frac_of_copy": step_gbs / copy_gbs, "torch_copy_gbs": torch_copy_gbs,
+        "compulsory_gbs": 2 * comp / (ms_step * 1e-3) / 1e9,
+        "note": "two field evaluations (forward with energy, backward) per step; whole-step time"}
     if not args.main_only:
         out["batched_multi_mesh"] = bench_batch(torch, tune=not args.no_tune, cache=args.schedule_cache)
         out["llg_rk4"] = bench_llg(torch, plan, m_np)

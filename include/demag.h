@@ -259,6 +259,13 @@ enum { DEMAG_TUNE_FORCE = 1 };    /* measure even where the cache has an entry *
 int demag_autotune(demag_plan* plan, const float* d_m, float* d_H, const char* cache_path, unsigned flags,
                    int* measured, void* stream);
 
+/* Plain streaming copy of `bytes` from d_src to d_dst on `stream` (device
+ * pointers, non-overlapping; both and `bytes` multiples of 16, else
+ * DEMAG_EINVAL): the HBM read + write rate of a trivially bandwidth-bound
+ * kernel, the measured ceiling the benchmark reports the field passes
+ * against.  Measurement only; not an operation of the method. */
+int demag_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* stream);
+
 /* Free a plan (host memory only).  NULL is accepted. */
 int demag_destroy(demag_plan* plan);
 

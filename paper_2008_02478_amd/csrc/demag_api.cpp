@@ -1219,6 +1219,14 @@ int demag_llg_rk4(const demag_plan* p, float* d_m, const demag_llg_params* prm, 
   return DEMAG_OK;
 }
 
+int demag_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* stream) {
+  if (!d_src || !d_dst) return fail(DEMAG_EINVAL, "demag_stream_copy: NULL buffer");
+  if ((bytes & 15) || (reinterpret_cast<uintptr_t>(d_src) & 15) || (reinterpret_cast<uintptr_t>(d_dst) & 15))
+    return fail(DEMAG_EINVAL, "demag_stream_copy: pointers and size must be multiples of 16 bytes");
+  const hipError_t e = launch_stream_copy(d_src, d_dst, bytes, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DEMAG_OK : fail_hip(e, "stream copy");
+}
+
 int demag_destroy(demag_plan* p) {
   delete p;
   return DEMAG_OK;

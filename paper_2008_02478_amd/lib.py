@@ -47,6 +47,7 @@ _SIGS = {
     "demag_llg_rk4": [_vp, _vp, ctypes.POINTER(LlgParams), _vp, _vp],
     "demag_setup_oersted": [ctypes.POINTER(_vp), _int, _int, _int, _dbl, _dbl, _dbl, _uint, _int],
     "demag_oersted_field": [_vp, _vp, _flt, _vp, _uint, _vp],
+    "demag_stream_copy": [_vp, _vp, ctypes.c_size_t, _vp],
     "demag_destroy": [_vp],
 }
 

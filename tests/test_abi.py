@@ -367,3 +367,11 @@ def test_oersted_plan_host_checks(lib):
     assert lib.demag_schedule_count(p, ctypes.byref(n)) == L.OK and n.value == 1
     lib.demag_destroy(p)
     lib.demag_destroy(q)
+
+
+def test_stream_copy_host_checks(lib):
+    d = ctypes.c_void_p(256)
+    assert lib.demag_stream_copy(None, d, 16, None) == L.EINVAL
+    assert lib.demag_stream_copy(d, None, 16, None) == L.EINVAL
+    assert lib.demag_stream_copy(d, d, 20, None) == L.EINVAL
+    assert lib.demag_stream_copy(ctypes.c_void_p(264), d, 16, None) == L.EINVAL
