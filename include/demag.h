@@ -229,7 +229,7 @@ int demag_oersted_field(const demag_plan* plan, const float* d_J, float scale, f
  *   radix points per lane of its y line FFTs (Ny/2 points per line): the
  *         default for the length, or 4 / 8 / 16 for Ny/2 of 256 and 512 when
  *         that leaves at most 64 lanes per line, or 8 for Ny/2 = 1024 (128
- *         lanes, a line spanning two wavefronts).
+ *         lanes, a line spanning two wavefronts; selectable, not tuned).
  * All schedules compute the same convolution (Sec. 3, Eq. 4); they differ
  * only in speed and FP32 rounding order.  Host only. */
 int demag_schedule_count(const demag_plan* plan, int* nparts);

@@ -583,11 +583,15 @@ int line_m(const Geom& g) { return g.Ny > 1 ? g.Ny / 2 : 1; }
 
 bool sched_ok(const Geom& g, int kw, int r) { return mid_schedule_ok(line_m(g), kw, r); }
 
+// Radices the tuner times.  Lines spanning two wavefronts (radix 8 at 1024
+// points) stay selectable by demag_set_schedule but are not tuned: timed alone
+// the middle pass looked faster with them, inside the field sequence it was
+// slower (422 vs 340 us at 1024x1024x4).
 std::vector<int> radix_candidates(const Geom& g) {
   const int M = line_m(g);
   std::vector<int> r{line_radix(M)};
   for (int c : {4, 8, 16})
-    if (c != r[0] && mid_radix_ok(M, c)) r.push_back(c);
+    if (c != r[0] && mid_radix_ok(M, c) && M / c <= 64) r.push_back(c);
   return r;
 }
 
