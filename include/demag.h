@@ -247,8 +247,9 @@ enum { DEMAG_TUNE_FORCE = 1 };    /* measure even where the cache has an entry *
 /* Launch-shape tuner.  For each part: if cache_path names a schedule cache
  * (JSON, "demag-schedule-cache/1") holding an entry for this device and
  * geometry, apply it; else time every candidate schedule on `stream` with
- * HIP events (x passes over the yg candidates, then the middle pass over
- * kw x radix), keep the fastest and, when cache_path is given, write it back
+ * HIP events (x passes over the yg candidates, then the whole field sequence
+ * over the middle pass's kw x radix), keep the fastest and, when cache_path
+ * is given, write it back
  * (temporary file + rename).  Measuring needs a bound plan (DEMAG_ESTATE) and,
  * for mesh parts, d_m and d_H laid out like the plan's vectors: d_m is only
  * read (its values do not matter), d_H and the plan's work buffer are

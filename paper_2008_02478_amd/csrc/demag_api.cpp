@@ -688,10 +688,14 @@ int tune_sub(demag_plan* p, Sub& sb, const float* d_m, float* d_H, hipStream_t s
       if (!sched_ok(g, kw, r)) continue;
       g.mid_kw = kw;
       g.mid_r = r;
+      // timed inside the whole field sequence: alone, the middle pass can
+      // rank its candidates differently (cache state, clocks)
       double us = 0.0;
       const int rc = time_calls(s, [&]() -> int {
-        const hipError_t e = launch_mid(g, mid_args(p, sb, false), s);
-        return e == hipSuccess ? DEMAG_OK : fail_hip(e, "middle pass");
+        hipError_t e = launch_fwd(g, fwd_args(p, sb, d_m, nullptr, 1.0f, nullptr), s);
+        if (e == hipSuccess) e = launch_mid(g, mid_args(p, sb, false), s);
+        if (e == hipSuccess) e = launch_inv(g, inv_plain_args(p, sb, d_H, 0u, nullptr), s);
+        return e == hipSuccess ? DEMAG_OK : fail_hip(e, "field sequence");
       }, us);
       if (rc != DEMAG_OK) {
         g.mid_kw = kw0;
@@ -709,7 +713,7 @@ int tune_sub(demag_plan* p, Sub& sb, const float* d_m, float* d_H, hipStream_t s
   g.mid_r = best_r;
   out.kw = best_kw;
   out.radix = best_r;
-  out.mid_us = best;
+  out.mid_us = best > out.x_us ? best - out.x_us : best;   // the middle pass's share of the sequence
   return DEMAG_OK;
 }
 
