@@ -33,6 +33,8 @@ CASES = [
     ((40, 20, 24), (4e-9, 4e-9, 2e-9)),
     ((24, 16, 40), (3e-9, 3e-9, 1e-9)),
     ((200, 150, 4), (2e-9, 2e-9, 1e-9)),
+    ((40, 600, 2), (4e-9, 2e-9, 3e-9)),             # 2048-point padded y lines
+    ((1500, 8, 1), (1e-9, 2e-9, 2e-9)),             # 4096-point padded x rows
 ]
 
 
