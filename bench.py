@@ -38,6 +38,7 @@ WORKLOADS = {
     "256x256x8": dict(n=(256, 256, 8), h=(4e-9, 4e-9, 4e-9), Ms=8e5, seed=2),
     "256x128x4": dict(n=(256, 128, 4), h=(5e-9, 5e-9, 2e-9), Ms=8e5, seed=4),
     "256x256x64": dict(n=(256, 256, 64), h=(4e-9, 4e-9, 4e-9), Ms=8e5, seed=12),
+    "64x64x1": dict(n=(64, 64, 1), h=(5e-9, 5e-9, 3e-9), Ms=8e5, seed=1),
 }
 
 
