@@ -97,7 +97,7 @@ def main():
         "achieved_GBs_algorithmic": a.algorithmic_bytes / (avg_ns * 1e-9) / 1e9,
         "source_hash": source_hash(),
     }
-    lines = [f"# {label} — {a.workload}", "", "Command (run from the repository root on the GPU box):", "",
+    lines = [f"# {label} — {a.workload}", "", "Command (run from the repository root on the MI355X machine):", "",
              "```", a.command, "```", "", "## Kernel trace (rocprofv3 --kernel-trace --stats)", "",
              "| kernel | calls | avg µs | min µs | max µs | % |", "|---|---|---|---|---|---|"]
     for r in rows:
