@@ -294,7 +294,7 @@ def main():
                     help="time the field + backward step only (no batch, RK4 or Oersted legs), e.g. under a profiler")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
 
     import torch
