@@ -18,7 +18,8 @@ Numerics (the paper is silent; the reading is recorded with the design notes):
     kernel D(v) = (|v|^2 I - 3 v v^T)/|v|^5, integrated by Gauss-Legendre
     quadrature on each half-axis [0, h_i] (the tent weight is smooth there):
     8 nodes per half-axis below 6 h_max, 6 below 16 h_max, 4 below 40 h_max,
-    3 beyond.  Measured against 60-digit evaluations this is <= 1e-11.
+    3 beyond.  Held to 1e-10 relative per entry in every band against the
+    closed form in 50-digit arithmetic (tests/test_oracle_farfield.py).
 
 Component order everywhere: xx, yy, zz, xy, xz, yz.
 """
