@@ -42,53 +42,78 @@ WORKLOADS = {
 }
 
 
-def mid_pass_bytes(n):
-    """Algorithmic HBM bytes of one middle-pass launch: read and write the
-    x/z-transformed spectrum of the three components (3 * Nz * (Nx/2+1) * ny
-    complex FP32) and read the kernel-spectrum octant once (6 * (Nz/2+1) *
-    (Ny/2+1) * (Nx/2+1) FP32)."""
-    from oracle.conv import padded_len  # plain arithmetic on sizes
+def _dims(n, padded):
+    """Padded lengths (the plan's, from demag_padded_dims) and the stored
+    half/octant extents Kx = Nx/2+1, Ky = Ny/2+1, Kz = Nz/2+1 (1 for unit
+    lengths)."""
+    Nx, Ny, Nz = padded
+    half = lambda N: N // 2 + 1 if N > 1 else 1
+    return Nx, Ny, Nz, half(Nx), half(Ny), half(Nz)
+
+
+def mid_pass_bytes(n, padded):
+    """Algorithmic HBM bytes of one middle-pass launch of this library's pass
+    order (z transformed in the x passes): read and write the x/z-transformed
+    spectrum of the three components (3 * Nz * (Nx/2+1) * ny complex FP32)
+    and read the kernel-spectrum octant once (6 * (Nz/2+1) * (Ny/2+1) *
+    (Nx/2+1) FP32)."""
     nx, ny, nz = n
-    Nx, Ny, Nz = padded_len(nx), padded_len(ny), padded_len(nz)
-    Kx = Nx // 2 + 1 if Nx > 1 else 1
-    Ky = Ny // 2 + 1 if Ny > 1 else 1
-    Kz = Nz // 2 + 1 if Nz > 1 else 1
+    Nx, Ny, Nz, Kx, Ky, Kz = _dims(n, padded)
     spec = 3 * Nz * Kx * ny * 8
     return 2 * spec + 6 * Kz * Ky * Kx * 4
 
 
-def mid_pass_flops(n):
+def model_mid_bytes(n, padded):
+    """Algorithmic HBM bytes of the fused middle step in the three-pass byte
+    model the measurement is held to (x / fused y-z-y / x): read and write
+    the x-transformed spectrum (3 * nz * (Nx/2+1) * ny complex FP32, z not yet
+    padded) and read the kernel octant once."""
+    nx, ny, nz = n
+    Nx, Ny, Nz, Kx, Ky, Kz = _dims(n, padded)
+    xspec = 3 * nz * Kx * ny * 8
+    return 2 * xspec + 6 * Kz * Ky * Kx * 4
+
+
+def mid_pass_flops(n, padded):
     """Algorithmic FP32 operations of one middle-pass launch, counting a
     complex M-point FFT as 5 M log2 M: per (kz, kx) line and component the two
     residue FFTs forward and inverse (M = Ny/2), the odd residue's twiddle each
     way (6 per point) and the residue sum (2 per point); per frequency the
     3x3 real-by-complex product (30)."""
     import math
-    from oracle.conv import padded_len  # plain arithmetic on sizes
-    nx, ny, nz = n
-    Nx, Ny, Nz = padded_len(nx), padded_len(ny), padded_len(nz)
-    Kx = Nx // 2 + 1 if Nx > 1 else 1
+    Nx, Ny, Nz, Kx, Ky, Kz = _dims(n, padded)
     M = Ny // 2 if Ny > 1 else 1
     fft = 5 * M * math.log2(M) if M > 1 else 0
     per_line = 3 * (4 * fft + 12 * M + 2 * M) + 30 * Ny
     return per_line * Nz * Kx
 
 
-def path_bytes(n):
-    """Per field evaluation: (algorithmic, compulsory) HBM bytes.  Algorithmic:
-    the three passes' reads and writes (M in, spectrum out; spectrum in and
-    out plus the kernel octant; spectrum in, H out).  Compulsory: read M and the
-    kernel octant once, write H."""
-    from oracle.conv import padded_len  # plain arithmetic on sizes
+def path_bytes(n, padded):
+    """Per field evaluation: (algorithmic, compulsory, three-pass model) HBM
+    bytes.  Algorithmic: this library's three passes' reads and writes (M in,
+    x/z spectrum out; that spectrum in and out plus the kernel octant;
+    spectrum in, H out).  Compulsory: read M and the kernel octant once, write
+    H.  Three-pass model: M in, x spectrum out; x spectrum in and out plus the
+    kernel octant; x spectrum in, H out."""
     nx, ny, nz = n
-    Nx, Ny, Nz = padded_len(nx), padded_len(ny), padded_len(nz)
-    Kx = Nx // 2 + 1 if Nx > 1 else 1
-    Ky = Ny // 2 + 1 if Ny > 1 else 1
-    Kz = Nz // 2 + 1 if Nz > 1 else 1
+    Nx, Ny, Nz, Kx, Ky, Kz = _dims(n, padded)
     vec = 3 * nx * ny * nz * 4
     spec = 3 * Nz * Kx * ny * 8
+    xspec = 3 * nz * Kx * ny * 8
     kern = 6 * Kz * Ky * Kx * 4
-    return 2 * vec + 4 * spec + kern, 2 * vec + kern
+    return 2 * vec + 4 * spec + kern, 2 * vec + kern, 2 * vec + 4 * xspec + kern
+
+
+def cpu_model():
+    """Model name of the host CPU (first entry of /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def bench_copy(torch, mib=1024, reps=10):
@@ -222,16 +247,12 @@ def bench_llg(torch, plan, m_np, steps=10):
             "params": {k: (list(v) if isinstance(v, tuple) else v) for k, v in kw.items()}}
 
 
-def oersted_mid_bytes(n):
+def oersted_mid_bytes(n, padded):
     """Algorithmic HBM bytes of one Oersted middle-pass launch: the spectrum
     read and written as for the demagnetizing field, and 3 kernel rows
     (instead of 6) per (kz, kx) of the octant."""
-    from oracle.conv import padded_len  # plain arithmetic on sizes
     nx, ny, nz = n
-    Nx, Ny, Nz = padded_len(nx), padded_len(ny), padded_len(nz)
-    Kx = Nx // 2 + 1 if Nx > 1 else 1
-    Ky = Ny // 2 + 1 if Ny > 1 else 1
-    Kz = Nz // 2 + 1 if Nz > 1 else 1
+    Nx, Ny, Nz, Kx, Ky, Kz = _dims(n, padded)
     return 2 * 3 * Nz * Kx * ny * 8 + 3 * Kz * Ky * Kx * 4
 
 
@@ -271,7 +292,7 @@ def bench_oersted(torch, n, h, seed, steps=30, tune=True, cache=None):
     pass_us = {"fwd_xz": 1e3 * float(np.mean([s[0].elapsed_time(s[1]) for s in evs])),
                "mid_y": 1e3 * float(np.mean([s[1].elapsed_time(s[2]) for s in evs])),
                "inv_zx": 1e3 * float(np.mean([s[2].elapsed_time(s[3]) for s in evs]))}
-    mb = oersted_mid_bytes(n)
+    mb = oersted_mid_bytes(n, plan.padded)
     ach = mb / (pass_us["mid_y"] * 1e-6) / 1e9
     return {"workload": f"Oersted field of a random current density on the {n[0]}x{n[1]}x{n[2]} mesh "
                         "(cell-averaged Biot-Savart kernel, open boundaries)",
@@ -376,8 +397,12 @@ def main():
         passes["mid_y"].append(s[1].elapsed_time(s[2]))
         passes["inv_zx"].append(s[2].elapsed_time(s[3]))
     pass_us = {k: 1e3 * float(np.mean(v)) for k, v in passes.items()}
-    mid_bytes = mid_pass_bytes(n)
-    achieved = mid_bytes / (pass_us["mid_y"] * 1e-6) / 1e9
+    padded = plan.padded
+    mid_bytes = mid_pass_bytes(n, padded)
+    model_bytes = model_mid_bytes(n, padded)
+    t_mid = pass_us["mid_y"] * 1e-6
+    achieved = model_bytes / t_mid / 1e9
+    flops = mid_pass_flops(n, padded)
     traffic = None
     valu = None
     side = os.path.join(ROOT, "profiles", f"k_mid_{args.workload}.json")
@@ -410,7 +435,7 @@ def main():
         "config": {
             "workload": f"{n[0]}x{n[1]}x{n[2]} mesh of {h[0]*1e9:g}x{h[1]*1e9:g}x{h[2]*1e9:g} nm cells, "
                         f"Ms={Ms:g} A/m, open boundaries; step = field+energy forward and <G,H> backward",
-            "mesh": list(n), "cell_m": list(h),
+            "mesh": list(n), "cell_m": list(h), "padded": list(padded),
         },
         "evals_per_s_fwd_bwd_pairs": 1e3 / ms_step,
         "pass_us": pass_us,
@@ -425,19 +450,29 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "algorithmic_bytes_per_launch": mid_bytes,
+            "algorithmic_bytes_per_launch": model_bytes,
+            "bytes_model": "three-pass model: x-transformed spectrum (3 nz (Nx/2+1) ny complex FP32) read and "
+                           "written once, kernel octant read once",
+            "this_pass_order": {
+                "algorithmic_bytes_per_launch": mid_bytes,
+                "achieved": mid_bytes / t_mid / 1e9,
+                "frac": mid_bytes / t_mid / 1e9 / HBM_PEAK_GBS,
+                "note": "z is transformed in the x passes, so the middle pass moves the z-padded spectrum "
+                        "(3 Nz (Nx/2+1) ny complex FP32) each way"},
             "valu": valu,
-            "alu": {"algorithmic_flop_per_launch": mid_pass_flops(n),
-                    "achieved_tflops": mid_pass_flops(n) / (pass_us["mid_y"] * 1e-6) / 1e12,
+            "alu": {"algorithmic_flop_per_launch": flops,
+                    "achieved_tflops": flops / t_mid / 1e12,
                     "peak_tflops": FP32_PEAK_TFLOPS,
-                    "frac": mid_pass_flops(n) / (pass_us["mid_y"] * 1e-6) / 1e12 / FP32_PEAK_TFLOPS},
+                    "frac": flops / t_mid / 1e12 / FP32_PEAK_TFLOPS},
         },
     }
 
-    alg, comp = path_bytes(n)
+    alg, comp, model = path_bytes(n, padded)
     copy_gbs, torch_copy_gbs = bench_copy(torch)
     step_gbs = 2 * alg / (ms_step * 1e-3) / 1e9
+    model_gbs = 2 * model / (ms_step * 1e-3) / 1e9
     out["path"] = {
+        "model_bytes_per_eval": model, "model_gbs": model_gbs, "model_frac_of_peak": model_gbs / HBM_PEAK_GBS,
         "algorithmic_bytes_per_eval": alg, "compulsory_bytes_per_eval": comp,
         "achieved_gbs": step_gbs, "frac_of_peak": step_gbs / HBM_PEAK_GBS,
         "copy_gbs": copy_gbs, "frac_of_copy": step_gbs / copy_gbs, "torch_copy_gbs": torch_copy_gbs,
@@ -456,20 +491,27 @@ def main():
         Nfull = tensor_full(n, h)
         tensor_s = time.time() - t0
         M = Ms * m_np.astype(np.float64)
-        t0 = time.time()
-        Hr = conv.fft_conv(M, h, Nfull)
-        gr = Ms * conv.fft_conv(G_np.astype(np.float64), h, Nfull)
-        cpu_s = time.time() - t0
+        times = []
+        for _ in range(3):
+            t0 = time.time()
+            Hr = conv.fft_conv(M, h, Nfull)
+            gr = Ms * conv.fft_conv(G_np.astype(np.float64), h, Nfull)
+            times.append(time.time() - t0)
+        cpu_s = float(np.median(times))
         Hg = H.cpu().numpy().astype(np.float64)
         gg = grad.cpu().numpy().astype(np.float64)
         out["cpu_baseline"] = {
             "value": ncell / cpu_s,
             "unit": "cell-updates/s (fwd+bwd)",
-            "cores": conv._WORKERS,
+            "cores": conv.fft_workers(),
             "kind": "oracle",
-            "sample": "one forward + backward step of the same workload by the FP64 oracle's FFT convolution "
-                      f"(tensor set-up excluded, {tensor_s:.1f} s)",
+            "sample": "one forward + backward step of the same workload by the FP64 oracle's FFT convolution, "
+                      f"median of 3 ({', '.join(f'{t:.2f}' for t in times)} s; tensor set-up excluded, "
+                      f"{tensor_s:.1f} s)",
             "seconds": cpu_s,
+            "threads": conv.fft_workers(),
+            "host_cpus": os.cpu_count(),
+            "cpu_model": cpu_model(),
         }
         out["accuracy"] = {
             "H_rel_l2_vs_fp64_oracle": float(np.linalg.norm(Hg - Hr) / np.linalg.norm(Hr)),

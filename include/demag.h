@@ -68,7 +68,10 @@ enum { DEMAG_ACCUMULATE = 1 };   /* H += H_d instead of H = H_d */
 int demag_setup(demag_plan** out, int nx, int ny, int nz, double dx, double dy, double dz,
                 unsigned pbc_flags, int pbc_images);
 
-/* Padded FFT lengths of the plan (powers of two >= 2n-1, or 1). */
+/* Padded FFT lengths of a single-mesh plan: powers of two >= 2n-1, or 1 for
+ * n = 1 (Sec. 7: zero padding to double the size; periodic axes are padded
+ * too, their image-summed tensor is convolved like an open one).  A batch
+ * plan has one padded size per geometry: DEMAG_EINVAL. */
 int demag_padded_dims(const demag_plan* plan, int* Nx, int* Ny, int* Nz);
 
 /* Bytes of the two device buffers the caller provides to demag_bind:
@@ -97,7 +100,12 @@ int demag_field(const demag_plan* plan, const float* d_m, const float* d_Ms, flo
                 unsigned flags, double* d_energy, void* stream);
 
 /* E = -(mu0/2) V sum_cells Ms m . H for a given field H (any H, e.g. an
- * accumulated effective field), written to the device double d_energy. */
+ * accumulated effective field), written to the device double d_energy.
+ * Appendix A: the field/energy relation H = -1/(mu0 Ms) d(eps)/dm gives, for
+ * the quadratic demagnetizing self-energy, the density eps = -(mu0/2) M . H.
+ * d_m, d_H: [3][nz][ny][nx] FP32; d_Ms: per-cell [nz][ny][nx] or NULL for the
+ * scalar Ms.  Products in FP32, sum in FP64 (fixed order).  Single-mesh plans
+ * only (DEMAG_EINVAL otherwise); DEMAG_ESTATE before demag_bind. */
 int demag_energy(const demag_plan* plan, const float* d_m, const float* d_Ms, float Ms, const float* d_H,
                  double* d_energy, void* stream);
 

@@ -23,6 +23,11 @@ MU0 = 4.0e-7 * math.pi
 _WORKERS = max(1, min(16, len(os.sched_getaffinity(0))))
 
 
+def fft_workers():
+    """Threads the FFT convolution uses."""
+    return _WORKERS
+
+
 def padded_len(n):
     """Smallest power of two >= 2n - 1 (open boundary), 1 for n == 1."""
     if n == 1:

@@ -914,6 +914,8 @@ int demag_batch_layout(const demag_plan* p, int* nmesh, long long* offsets, size
 
 int demag_padded_dims(const demag_plan* p, int* Nx, int* Ny, int* Nz) {
   if (!p || !Nx || !Ny || !Nz) return fail(DEMAG_EINVAL, "demag_padded_dims: NULL argument");
+  if (p->batch || p->subs.size() != 1)
+    return fail(DEMAG_EINVAL, "demag_padded_dims: a batch plan has one padded size per geometry");
   *Nx = p->subs[0].g.Nx; *Ny = p->subs[0].g.Ny; *Nz = p->subs[0].g.Nz;
   return DEMAG_OK;
 }

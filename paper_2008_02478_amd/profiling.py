@@ -24,12 +24,19 @@ import re
 import statistics
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["csrc/k_field.hip", "csrc/fft_core.hpp", "csrc/plan.hpp"]
+def kernel_sources():
+    """Every source of the library (kernels, headers, host code), sorted."""
+    d = os.path.join(PKG, "csrc")
+    return sorted(os.path.join("csrc", f) for f in os.listdir(d)
+                  if f.endswith((".hip", ".hpp", ".cpp", ".h")))
 
 
 def source_hash():
+    """Hash of every library source, so counters taken from another build are
+    recognised as stale."""
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in kernel_sources():
+        h.update(rel.encode())
         with open(os.path.join(PKG, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -375,3 +375,54 @@ def test_stream_copy_host_checks(lib):
     assert lib.demag_stream_copy(d, None, 16, None) == L.EINVAL
     assert lib.demag_stream_copy(d, d, 20, None) == L.EINVAL
     assert lib.demag_stream_copy(ctypes.c_void_p(264), d, 16, None) == L.EINVAL
+
+
+def test_padded_dims_refuses_batch_plans(lib):
+    # a batch whose meshes all belong to one coupled group has no single padded size
+    dims = (ctypes.c_int * 6)(8, 8, 1, 8, 8, 1)
+    cells = (ctypes.c_double * 6)(1e-9, 1e-9, 1e-9, 1e-9, 1e-9, 1e-9)
+    origin = (ctypes.c_double * 6)(0, 0, 0, 0, 0, 2e-9)
+    group = (ctypes.c_int * 2)(0, 0)
+    p = ctypes.c_void_p()
+    assert lib.demag_setup_batch(ctypes.byref(p), 2, dims, cells, origin, group, 0, 0) == L.OK
+    try:
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        assert lib.demag_padded_dims(p, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)) == L.EINVAL
+    finally:
+        lib.demag_destroy(p)
+    # independent meshes of two geometries: also refused
+    dims = (ctypes.c_int * 6)(8, 8, 1, 4, 4, 2)
+    assert lib.demag_setup_batch(ctypes.byref(p), 2, dims, cells, None, None, 0, 0) == L.OK
+    try:
+        assert lib.demag_padded_dims(p, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)) == L.EINVAL
+    finally:
+        lib.demag_destroy(p)
+
+
+def test_xpass_classes_skipped_on_the_gpu_are_rejected_for_every_mesh(lib):
+    # tests/test_gpu_xpass.py runs one mesh per (log2 Nx, log2 Nz) class the
+    # library accepts; a class whose representative is rejected must be
+    # rejected for every nx and nz in it (the limits only grow with nx, nz)
+    from tests.xpass_classes import representatives, padded
+
+    def ok(nx, ny, nz):
+        p = ctypes.c_void_p()
+        rc = lib.demag_setup(ctypes.byref(p), nx, ny, nz, 3e-9, 2e-9, 1e-9, 0, 0)
+        if rc == L.OK:
+            lib.demag_destroy(p)
+        return rc == L.OK
+
+    n_acc = 0
+    for (a, b), (nx, ny, nz) in representatives():
+        assert padded(nx) == 1 << a and padded(nz) == 1 << b
+        lo_x = 1 if a == 0 else (2 if a == 2 else (1 << (a - 2)) + 1)
+        lo_z = 1 if b == 0 else (2 if b == 2 else (1 << (b - 2)) + 1)
+        assert nz == lo_z
+        if ok(nx, ny, nz):
+            n_acc += 1
+            continue
+        for x in (lo_x, nx, 1 << max(a - 1, 0)):
+            for z in (lo_z, 1 << max(b - 1, 0)):
+                if padded(x) == 1 << a and padded(z) == 1 << b:
+                    assert not ok(x, ny, z), (a, b, x, z)
+    assert n_acc >= 70

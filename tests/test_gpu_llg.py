@@ -61,7 +61,9 @@ def test_rk4_trajectory_matches_oracle(torch, n, h, pbc, steps):
     mg = m.cpu().numpy()
     err = rel_l2(mg - m0, mr - m0)
     say(f"  change of m: rel-L2 {err:.2e}; |m| - 1 <= {np.max(np.abs(np.linalg.norm(mg, axis=0) - 1)):.1e}")
-    assert err < 1e-4
+    # the change of m over the run carries the FP32 round-off of every
+    # stage (measured 2e-7 to 4e-6); held to the field's 1e-5 target
+    assert err < TOL
     assert rel_l2(mg, mr) < TOL
 
 
