@@ -398,8 +398,16 @@ int build_spectrum(const Geom& g, float* d_K, hipStream_t s) {
   for (int a = 0; a < 3; ++a)
     for (int m = 0; m < Ns[a]; ++m) {
       const double ang = 2.0 * M_PI * m / Ns[a];
-      trig[(size_t)(2 * a) * Nmax + m] = std::cos(ang);
-      trig[(size_t)(2 * a + 1) * Nmax + m] = std::sin(ang);
+      double c = std::cos(ang), sn = std::sin(ang);
+      if ((4 * m) % Ns[a] == 0) {
+        // multiples of a quarter turn exactly, so that the odd components'
+        // sine transforms vanish exactly at the Nyquist frequency
+        const int q = 4 * m / Ns[a];
+        c = q == 0 ? 1.0 : (q == 2 ? -1.0 : 0.0);
+        sn = q == 1 ? 1.0 : (q == 3 ? -1.0 : 0.0);
+      }
+      trig[(size_t)(2 * a) * Nmax + m] = c;
+      trig[(size_t)(2 * a + 1) * Nmax + m] = sn;
     }
   GLTable gl{};
   const int orders[4] = {8, 6, 4, 3};

@@ -287,6 +287,24 @@ __device__ __forceinline__ void residue_twiddle(float2 (&v)[R], float2 base, boo
   residue_twiddle_j<R, 0, INV>(v, base, on);
 }
 
+// Odd-residue twiddles of an M-point line: the odd outputs of a 2M-point
+// transform of M non-zero points are the M-point transform of x[n] W_2M^n.
+// rtab[k] = W_2M^k for k < M, filled cooperatively into LDS.
+template <int M>
+__device__ __forceinline__ void fill_residue_table(float2* __restrict__ rtab, const float2* __restrict__ tw,
+                                                   int tid, int nth) {
+  for (int k = tid; k < M; k += nth) rtab[k] = twiddle<false>(tw, k, ilog2(2 * M));
+}
+// v[j] *= rtab[t + T j] (INV: conjugate), stride-T layout of lane t.
+template <int R, int T, bool INV>
+__device__ __forceinline__ void residue_twiddle_tab(float2 (&v)[R], const float2* __restrict__ rtab, int t) {
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const float2 w = rtab[t + T * j];
+    v[j] = INV ? cmulc(v[j], w) : cmul(v[j], w);
+  }
+}
+
 // Points per lane used for an M-point line.
 template <int M>
 struct LineShape {

@@ -157,6 +157,10 @@ __device__ __forceinline__ int kz_of(int i, int Nz) {
 // threads of the middle pass: two residue jobs per kx (one for a unit y
 // length), each a group of LineShape<M>::T lanes, at least one wavefront
 constexpr int mid_radix_of(int lny) { return line_radix(lny > 0 ? (1 << lny) / 2 : 1); }
+// LDS points of the middle pass' odd-residue twiddle table (M entries, padded
+// to 32 points so the data after it stays 256-byte aligned)
+template <int M, int NRES>
+constexpr int mid_rtab_points() { return NRES == 2 ? ((M + 31) / 32) * 32 : 0; }
 constexpr int mid_threads(int lny, int kw, int r) { return mid_threads_rt(lny > 0 ? (1 << lny) / 2 : 1, kw, r); }
 
 template <typename Tv>
@@ -192,7 +196,8 @@ k_mid(MidArgs a) {
   __shared__ double red[16];
   extern __shared__ float2 smem_base[];
   float2* const tab = smem_base;
-  float2* const smem = smem_base + tab_points<M, R>();
+  float2* const rtab = smem_base + tab_points<M, R>();      // odd-residue twiddles W_2M^k, k < M
+  float2* const smem = rtab + mid_rtab_points<M, NRES>();
 
   const int lg0 = xcd_logical(blockIdx.x, gridDim.x);
   const int bm = lg0 / a.nblk1;             // batch member
@@ -212,7 +217,11 @@ k_mid(MidArgs a) {
   const bool lane_act = tid < NT;
   const int job = (T >= 64) ? __builtin_amdgcn_readfirstlane(tid / T) : tid / T;
   const int t = tid % T;
-  const int w = job / NRES, r = job % NRES;
+  // jobs r-major: the KW lines of residue 0, then those of residue 1, so
+  // that the residue is uniform over a wavefront when KW T >= 64
+  constexpr bool R_UNIFORM = (KW * T) % 64 == 0;
+  const int w = job % KW;
+  const int r = NRES == 1 ? 0 : (R_UNIFORM ? __builtin_amdgcn_readfirstlane(tid / (KW * T)) : job / KW);
   const int kx = tile * TILE + half * KW + w;
   const bool valid = lane_act && kx < a.Kx;
   if (tile * TILE + half * KW >= a.Kx) {    // nothing but padding columns
@@ -229,7 +238,7 @@ k_mid(MidArgs a) {
   float2* blk0 = a.T + ((size_t)kz * a.nTiles + tile) * ny * TILE + half * KW;
 
   if constexpr (M > R) fill_stage_table<M, R>(tab, a.tw, tid, blockDim.x);
-  const float2 rbase = twiddle<false>(a.tw, t, ilog2(2 * M));
+  if constexpr (NRES == 2) fill_residue_table<M>(rtab, a.tw, tid, blockDim.x);
 
   // The kernel spectrum of this workgroup (KW consecutive kx lines of NKC rows
   // of KYP floats, contiguous in K[kz][kx][c][ky], plus their NKC KW Nyquist
@@ -312,7 +321,12 @@ k_mid(MidArgs a) {
         const int y = t + T * j;
         v[c][j] = (valid && y < ny) ? stage[c * ny * KWP + y * KWP + w] : make_float2(0.f, 0.f);
       }
-      if constexpr (NRES == 2) residue_twiddle<R, false>(v[c], rbase, r != 0);
+    }
+    if constexpr (NRES == 2) {
+      if (r) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) residue_twiddle_tab<R, T, false>(v[c], rtab, t);
+      }
     }
     __syncthreads();
     if (lane_act) {
@@ -334,6 +348,10 @@ k_mid(MidArgs a) {
   // is split by the parity of ky (the parity of a job's folded ky is its
   // residue r), so the lanes of a job read consecutive words.
   float* const kl = reinterpret_cast<float*>(smem);   // aliases stage and FFT scratch
+  // kernel rows odd in z (xz, yz; the Oersted P_z) change sign for kz > Nz/2:
+  // folded in while the rows move to LDS
+  constexpr unsigned ZODD = MODE == 3 ? 0x4u : 0x30u;
+  const float sz = (kz <= a.Nz / 2) ? 1.f : -1.f;
   if constexpr (PROD) {
     __syncthreads();   // every job is done with its forward FFT scratch
 #pragma unroll
@@ -341,6 +359,9 @@ k_mid(MidArgs a) {
       const int e = tid + i * NTHK;
       if (e < KF4) {
         const int row = (4 * e) / KYP, ky0 = 4 * e - row * KYP;
+        if ((ZODD >> (row % NKC)) & 1u) {
+          kp[i].x *= sz; kp[i].y *= sz; kp[i].z *= sz; kp[i].w *= sz;
+        }
         float* const dst = kl + row * KLP;
         if constexpr (NRES == 2) {
           *reinterpret_cast<float2*>(dst + ky0 / 2) = make_float2(kp[i].x, kp[i].z);
@@ -350,31 +371,22 @@ k_mid(MidArgs a) {
         }
       }
     }
-    if (NY >= 4 && tid < NKC * KW) kl[tid * KLP + KYP / 2] = knv;
+    if (NY >= 4 && tid < NKC * KW) kl[tid * KLP + KYP / 2] = ((ZODD >> (tid % NKC)) & 1u) ? sz * knv : knv;
     __syncthreads();
   }
   double e = 0.0;
   if (lane_act && PROD) {
-    const float sz = (kz <= a.Nz / 2) ? 1.f : -1.f;
     const float* const Kb = kl + w * NKC * KLP;
     const float wkx = (kx == 0 || 2 * kx == a.Nx) ? 1.f : 2.f;
     float ef = 0.f;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const int ky = NRES * (t + T * j) + r;
-      const bool lo = 2 * ky <= NY;
-      const int kyf = lo ? ky : NY - ky;
-      // index in the LDS row: even/odd half by the residue, the Nyquist
-      // entry at KYP/2 (which the even-half index reaches by itself for
-      // Ny >= 8)
-      int ki = NRES == 2 ? (r ? OH : 0) + (kyf >> 1) : kyf;
-      if constexpr (NY == 4) ki = kyf == 2 ? KYP / 2 : ki;
-      const float sy = lo ? 1.f : -1.f;
+    // 3x3 product at one frequency: kernel entries k[0..NKC) read at row
+    // offset ki of this line's NKC rows, sy the sign of the rows odd in y
+    auto product = [&](int j, const float* kp0, float sy) __attribute__((always_inline)) {
       if constexpr (MODE == 3) {
         // H^ = i (P x J^), P real: i (a + i b) = -b + i a
-        const float px = Kb[0 * KLP + ki];
-        const float py = sy * Kb[1 * KLP + ki];
-        const float pz = sz * Kb[2 * KLP + ki];
+        const float px = kp0[0 * KLP];
+        const float py = sy * kp0[1 * KLP];
+        const float pz = kp0[2 * KLP];
         const float2 jx = v[0][j], jy = v[1][j], jz = v[2][j];
         const float2 cx = make_float2(py * jz.x - pz * jy.x, py * jz.y - pz * jy.y);
         const float2 cy = make_float2(pz * jx.x - px * jz.x, pz * jx.y - px * jz.y);
@@ -382,21 +394,48 @@ k_mid(MidArgs a) {
         v[0][j] = make_float2(-cx.y, cx.x);
         v[1][j] = make_float2(-cy.y, cy.x);
         v[2][j] = make_float2(-cz.y, cz.x);
-        continue;
+      } else {
+        const float kxx = kp0[0 * KLP];
+        const float kyy = kp0[1 * KLP];
+        const float kzz = kp0[2 * KLP];
+        const float kxy = sy * kp0[3 * KLP];
+        const float kxz = kp0[4 * KLP];
+        const float kyz = sy * kp0[5 * KLP];
+        const float2 mx = v[0][j], my = v[1][j], mz = v[2][j];
+        const float2 hx = make_float2(kxx * mx.x + kxy * my.x + kxz * mz.x, kxx * mx.y + kxy * my.y + kxz * mz.y);
+        const float2 hy = make_float2(kxy * mx.x + kyy * my.x + kyz * mz.x, kxy * mx.y + kyy * my.y + kyz * mz.y);
+        const float2 hz = make_float2(kxz * mx.x + kyz * my.x + kzz * mz.x, kxz * mx.y + kyz * my.y + kzz * mz.y);
+        if constexpr (ENERGY)
+          ef += mx.x * hx.x + mx.y * hx.y + my.x * hy.x + my.y * hy.y + mz.x * hz.x + mz.y * hz.y;
+        v[0][j] = hx; v[1][j] = hy; v[2][j] = hz;
       }
-      const float kxx = Kb[0 * KLP + ki];
-      const float kyy = Kb[1 * KLP + ki];
-      const float kzz = Kb[2 * KLP + ki];
-      const float kxy = sy * Kb[3 * KLP + ki];
-      const float kxz = sz * Kb[4 * KLP + ki];
-      const float kyz = sy * sz * Kb[5 * KLP + ki];
-      const float2 mx = v[0][j], my = v[1][j], mz = v[2][j];
-      const float2 hx = make_float2(kxx * mx.x + kxy * my.x + kxz * mz.x, kxx * mx.y + kxy * my.y + kxz * mz.y);
-      const float2 hy = make_float2(kxy * mx.x + kyy * my.x + kyz * mz.x, kxy * mx.y + kyy * my.y + kyz * mz.y);
-      const float2 hz = make_float2(kxz * mx.x + kyz * my.x + kzz * mz.x, kxz * mx.y + kyz * my.y + kzz * mz.y);
-      if constexpr (ENERGY)
-        ef += mx.x * hx.x + mx.y * hx.y + my.x * hy.x + my.y * hy.y + mz.x * hz.x + mz.y * hz.y;
-      v[0][j] = hx; v[1][j] = hy; v[2][j] = hz;
+    };
+    if constexpr (NRES == 2 && NY >= 8) {
+      // ky = 2u + r with u = t + T j.  For j < R/2, ky < NY/2: folded
+      // ky = ky, row index u in the residue's half.  For j >= R/2 the
+      // frequency folds to NY - ky, row index M - u - r, sign -1 for the rows
+      // odd in y (at ky = NY/2, reached by t = r = 0, j = R/2, those rows are
+      // zero, so the sign does not matter there).  Both indices are affine in
+      // t with compile-time offsets per j.
+      const float* const plo = Kb + (r ? OH : 0) + t;
+      const float* const phi = Kb + (r ? OH : 0) + M - r - t;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if (j < R / 2) product(j, plo + T * j, 1.f);
+        else product(j, phi - T * j, -1.f);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int ky = NRES * (t + T * j) + r;
+        const bool lo = 2 * ky <= NY;
+        const int kyf = lo ? ky : NY - ky;
+        // index in the LDS row: even/odd half by the residue, the Nyquist
+        // entry at KYP/2
+        int ki = NRES == 2 ? (r ? OH : 0) + (kyf >> 1) : kyf;
+        if constexpr (NY == 4) ki = kyf == 2 ? KYP / 2 : ki;
+        product(j, Kb + ki, lo ? 1.f : -1.f);
+      }
     }
     if (ENERGY && valid) e = (double)(wkx * ef);
   }
@@ -405,7 +444,12 @@ k_mid(MidArgs a) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       group_fft<M, R, true>(v[c], scr, t, tab);
-      if constexpr (NRES == 2) residue_twiddle<R, true>(v[c], rbase, r != 0);
+    }
+    if constexpr (NRES == 2) {
+      if (r) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) residue_twiddle_tab<R, T, true>(v[c], rtab, t);
+      }
     }
   }
 
@@ -707,7 +751,7 @@ static hipError_t mid_launch(const Geom& g, const MidArgs& a, hipStream_t s) {
   const size_t klp = NRES == 2 ? kernel_row_pitch(NY) + 4 : kernel_row_pitch(NY);
   const size_t kr = (MODE == 0 || MODE == 3) ? (size_t)KW * (MODE == 3 ? 3 : 6) * klp * sizeof(float) : 0;
   if (kr > lds) lds = kr;
-  lds += tab_points<M, R>() * sizeof(float2);
+  lds += (tab_points<M, R>() + mid_rtab_points<M, NRES>()) * sizeof(float2);
   hipError_t e = prep_lds(k_mid<LNY, KW, ENERGY, MODE, R>, lds);
   if (e != hipSuccess) return e;
   const int blocks = g.nTiles * (TILE / KW) * g.Nz;
