@@ -86,7 +86,10 @@ int demag_buffer_bytes(const demag_plan* plan, size_t* kernel_bytes, size_t* wor
  * (Sec. 3 Eq. 4; Table 1), its transform on the padded grid in FP64, stored in
  * FP32 with the factor -1/(Nx Ny Nz).  Set-up only: allocates FP64
  * temporaries, synchronizes `stream` and frees them before returning.  A plan
- * binds once (DEMAG_ESTATE otherwise). */
+ * binds once (DEMAG_ESTATE otherwise).  d_work may be NULL for a
+ * single-mesh demagnetizing plan: it can then be used only with
+ * demag_field_noalloc (every call that needs the work buffer returns
+ * DEMAG_ESTATE). */
 int demag_bind(demag_plan* plan, void* d_kernel, void* d_work, void* stream);
 
 /* H_d = -N * M with M = Ms * m (Table 1, demagnetizing field).  d_m: unit
@@ -98,6 +101,27 @@ int demag_bind(demag_plan* plan, void* d_kernel, void* d_work, void* stream);
  * not overlap. */
 int demag_field(const demag_plan* plan, const float* d_m, const float* d_Ms, float Ms, float* d_H,
                 unsigned flags, double* d_energy, void* stream);
+
+/* Size of the library's static work space per GPU (64 MiB), the limit of
+ * demag_field_noalloc. */
+#define DEMAG_NOALLOC_WORK_BYTES (64u << 20)
+
+/* demag_field for callers that cannot allocate device memory while they run
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same passes, with the spectrum and energy partials in a
+ * static device array of DEMAG_NOALLOC_WORK_BYTES that each GPU holds for the
+ * lifetime of the process, instead of the plan's work buffer.  Arguments,
+ * layouts and results are those of demag_field (bitwise the same output).
+ * Single-mesh demagnetizing plans only (DEMAG_EINVAL otherwise), bound on the
+ * current device (DEMAG_EINVAL for another device; DEMAG_ESTATE before
+ * demag_bind), whose work_bytes (demag_buffer_bytes) are at most
+ * DEMAG_NOALLOC_WORK_BYTES (DEMAG_EUNSUPPORTED otherwise, checked before the
+ * bind state).  Calls no allocator.  All calls on one GPU share that GPU's
+ * array, which keeps the last call's contents: calls that overlap in time on
+ * one GPU (other streams, other threads, other plans) race and give wrong
+ * results; order them on one stream. */
+int demag_field_noalloc(const demag_plan* plan, const float* d_m, const float* d_Ms, float Ms, float* d_H,
+                        unsigned flags, double* d_energy, void* stream);
 
 /* E = -(mu0/2) V sum_cells Ms m . H for a given field H (any H, e.g. an
  * accumulated effective field), written to the device double d_energy.

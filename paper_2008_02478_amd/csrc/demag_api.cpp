@@ -12,6 +12,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -66,7 +67,9 @@ struct demag_plan {
   std::vector<long long> offsets;    // float offset of each mesh in concatenated buffers
   size_t total_floats = 0;
   bool bound = false;
+  bool has_work = false;             // bound with a work buffer (else demag_field_noalloc only)
   int device = -1;
+  char* noalloc_work = nullptr;      // this device's static scratch (demag_field_noalloc)
   float2* tw = nullptr;
   size_t kernel_bytes = 0, work_bytes = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -89,6 +92,32 @@ int fail_hip(hipError_t e, const char* what) {
 }
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Work space of demag_field_noalloc: the spectrum and energy partials of one
+// single-mesh plan, in a device array of fixed size instead of a buffer the
+// caller allocates.  Every GPU the library runs on holds its own copy until
+// the process ends.  In host code the array's name is only a stand-in: its
+// device address, per device, comes from hipGetSymbolAddress, taken once per
+// device with that device current (at the first demag_bind on it) and kept
+// in scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[DEMAG_NOALLOC_WORK_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+char* scratch_ptr[MAX_DEVICES] = {};
+
+int noalloc_scratch(int dev, char** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(DEMAG_EUNSUPPORTED, "device index out of range for the static scratch");
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(DEMAG_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = scratch_ptr[dev];
+  return DEMAG_OK;
+}
 
 int padded(int n) {
   if (n == 1) return 1;
@@ -497,42 +526,61 @@ int mark(const demag_plan* p, int i, hipStream_t s) {
   return e == hipSuccess ? DEMAG_OK : fail_hip(e, "hipEventRecord");
 }
 
+// Where a sub-plan's spectrum and energy partials live: the bound work buffer,
+// or the same offsets into another base (the static scratch of
+// demag_field_noalloc).
+struct Slab {
+  float2* T;
+  double* epart;
+};
+
+Slab slab_of(const Sub& sb, char* base) {
+  if (!base) return Slab{sb.T, sb.epart};
+  return Slab{reinterpret_cast<float2*>(base + sb.t_off), reinterpret_cast<double*>(base + sb.e_off)};
+}
+
 FwdArgs fwd_args(const demag_plan* p, const Sub& sb, const float* src, const float* Ms, float ms,
-                 const float* ms_mesh, const float* src2 = nullptr, float ms2 = 0.f) {
+                 const float* ms_mesh, const float* src2 = nullptr, float ms2 = 0.f, char* base = nullptr) {
   const Geom& g = sb.g;
-  return FwdArgs{src, Ms, ms, sb.T, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, (int)sb.members.size(),
+  return FwdArgs{src, Ms, ms, slab_of(sb, base).T, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, (int)sb.members.size(),
                  p->batch ? sb.moff : nullptr, ms_mesh, spectrum_elems(g), p->batch ? sb.gid : nullptr,
                  src2, ms2};
 }
 
-MidArgs mid_args(const demag_plan* p, const Sub& sb, bool energy) {
+MidArgs mid_args(const demag_plan* p, const Sub& sb, bool energy, char* base = nullptr) {
   const Geom& g = sb.g;
-  return MidArgs{sb.T, sb.K, p->tw, energy ? sb.epart : nullptr, g.ny, g.Nz, g.Nx, g.nTiles, g.Kx, g.Kyh, g.Kzh,
+  const Slab w = slab_of(sb, base);
+  return MidArgs{w.T, sb.K, p->tw, energy ? w.epart : nullptr, g.ny, g.Nz, g.Nx, g.nTiles, g.Kx, g.Kyh, g.Kzh,
                  TILE / mid_kw(g), (int)sb.members.size(), spectrum_elems(g), mid_blocks(g)};
 }
 
 // forward and middle passes of one sub-plan (src2: optional second sublattice)
 int run_conv(const demag_plan* p, const Sub& sb, const float* src, const float* Ms, float ms,
-             const float* ms_mesh, bool energy, hipStream_t s, const float* src2 = nullptr, float ms2 = 0.f) {
+             const float* ms_mesh, bool energy, hipStream_t s, const float* src2 = nullptr, float ms2 = 0.f,
+             char* base = nullptr) {
   const Geom& g = sb.g;
   int rc = mark(p, 0, s);
   if (rc != DEMAG_OK) return rc;
-  hipError_t e = launch_fwd(g, fwd_args(p, sb, src, Ms, ms, ms_mesh, src2, ms2), s);
+  hipError_t e = launch_fwd(g, fwd_args(p, sb, src, Ms, ms, ms_mesh, src2, ms2, base), s);
   if (e != hipSuccess) return fail_hip(e, "forward pass");
   if ((rc = mark(p, 1, s)) != DEMAG_OK) return rc;
-  e = launch_mid(g, mid_args(p, sb, energy), s);
+  e = launch_mid(g, mid_args(p, sb, energy, base), s);
   if (e != hipSuccess) return fail_hip(e, "middle pass");
   return mark(p, 2, s);
 }
 
+// base: NULL for the bound work buffer, else the base of another buffer with
+// the same layout (the static scratch of demag_field_noalloc)
 int run_field(const demag_plan* p, const float* d_m, const float* d_Ms, float Ms, const float* ms_mesh, float* d_H,
-              unsigned flags, double* d_energy, hipStream_t s, const float* d_m2 = nullptr, float Ms2 = 0.f) {
+              unsigned flags, double* d_energy, hipStream_t s, const float* d_m2 = nullptr, float Ms2 = 0.f,
+              char* base = nullptr) {
   for (const Sub& sb : p->subs) {
     const Geom& g = sb.g;
     const int nb = (int)sb.members.size();
-    int rc = run_conv(p, sb, d_m, d_Ms, Ms, ms_mesh, d_energy != nullptr, s, d_m2, Ms2);
+    const Slab w = slab_of(sb, base);
+    int rc = run_conv(p, sb, d_m, d_Ms, Ms, ms_mesh, d_energy != nullptr, s, d_m2, Ms2, base);
     if (rc != DEMAG_OK) return rc;
-    InvArgs ia{sb.T, d_H, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, (flags & DEMAG_ACCUMULATE) ? 1 : 0,
+    InvArgs ia{w.T, d_H, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, (flags & DEMAG_ACCUMULATE) ? 1 : 0,
                nullptr, nullptr, 0.0, nullptr, 0.f, 0,
                nb, p->batch ? sb.moff : nullptr, ms_mesh, spectrum_elems(g), p->batch ? sb.gid : nullptr};
     hipError_t e = launch_inv(g, ia, s);
@@ -540,7 +588,7 @@ int run_field(const demag_plan* p, const float* d_m, const float* d_Ms, float Ms
     if ((rc = mark(p, 3, s)) != DEMAG_OK) return rc;
     if (d_energy) {
       const double V = g.dx * g.dy * g.dz;
-      e = launch_energy_final(sb.epart, mid_blocks(g), -0.5 * MU0 * V, d_energy, s, nb, p->batch ? sb.gid : nullptr);
+      e = launch_energy_final(w.epart, mid_blocks(g), -0.5 * MU0 * V, d_energy, s, nb, p->batch ? sb.gid : nullptr);
       if (e != hipSuccess) return fail_hip(e, "energy reduction");
     }
   }
@@ -938,11 +986,18 @@ int demag_buffer_bytes(const demag_plan* p, size_t* kernel_bytes, size_t* work_b
 int demag_bind(demag_plan* p, void* d_kernel, void* d_work, void* stream) {
   if (!p) return fail(DEMAG_EINVAL, "demag_bind: plan is NULL");
   if (p->bound) return fail(DEMAG_ESTATE, "demag_bind: plan is already bound");
-  if (!d_kernel || !d_work) return fail(DEMAG_EINVAL, "demag_bind: NULL buffer");
-  if (!aligned(d_kernel) || !aligned(d_work)) return fail(DEMAG_EINVAL, "demag_bind: buffers must be 256-byte aligned");
+  if (!d_kernel) return fail(DEMAG_EINVAL, "demag_bind: NULL kernel buffer");
+  if (!d_work && (p->batch || p->oersted))
+    return fail(DEMAG_EINVAL, "demag_bind: only single-mesh demagnetizing plans may be bound without a work buffer");
+  if (!aligned(d_kernel) || (d_work && !aligned(d_work)))
+    return fail(DEMAG_EINVAL, "demag_bind: buffers must be 256-byte aligned");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  {
+    const int rc = noalloc_scratch(p->device, &p->noalloc_work);
+    if (rc != DEMAG_OK) return rc;
+  }
   char* kb = static_cast<char*>(d_kernel);
   char* wb = static_cast<char*>(d_work);
 
@@ -958,8 +1013,8 @@ int demag_bind(demag_plan* p, void* d_kernel, void* d_work, void* stream) {
     sb.K = reinterpret_cast<float*>(kb + sb.k_off);
     sb.moff = reinterpret_cast<long long*>(kb + sb.tab_off);
     sb.gid = reinterpret_cast<int*>(kb + sb.tab_off + align256(sb.members.size() * sizeof(long long)));
-    sb.T = reinterpret_cast<float2*>(wb + sb.t_off);
-    sb.epart = reinterpret_cast<double*>(wb + sb.e_off);
+    sb.T = wb ? reinterpret_cast<float2*>(wb + sb.t_off) : nullptr;
+    sb.epart = wb ? reinterpret_cast<double*>(wb + sb.e_off) : nullptr;
     std::vector<long long> mo;
     for (int m : sb.members) mo.push_back(p->offsets[m]);
     if ((e = hipMemcpyAsync(sb.moff, mo.data(), mo.size() * sizeof(long long), hipMemcpyHostToDevice, s)) != hipSuccess ||
@@ -983,6 +1038,7 @@ int demag_bind(demag_plan* p, void* d_kernel, void* d_work, void* stream) {
     if (rc != DEMAG_OK) return rc;
   }
   p->bound = true;
+  p->has_work = wb != nullptr;
   return DEMAG_OK;
 }
 
@@ -992,10 +1048,32 @@ int demag_field(const demag_plan* p, const float* d_m, const float* d_Ms, float 
   if (p->oersted) return fail(DEMAG_EINVAL, "demag_field: an Oersted plan (use demag_oersted_field)");
   if (p->batch) return fail(DEMAG_EINVAL, "demag_field: batch plans use demag_field_batch");
   if (!p->bound) return fail(DEMAG_ESTATE, "demag_field: plan is not bound");
+  if (!p->has_work) return fail(DEMAG_ESTATE, "demag_field: plan was bound without a work buffer");
   if (!d_m || !d_H) return fail(DEMAG_EINVAL, "demag_field: NULL m or H");
   if (flags & ~(unsigned)DEMAG_ACCUMULATE) return fail(DEMAG_EINVAL, "demag_field: unknown flags");
   if (!d_Ms && !std::isfinite(Ms)) return fail(DEMAG_EINVAL, "demag_field: Ms is not finite");
   return run_field(p, d_m, d_Ms, Ms, nullptr, d_H, flags, d_energy, static_cast<hipStream_t>(stream));
+}
+
+int demag_field_noalloc(const demag_plan* p, const float* d_m, const float* d_Ms, float Ms, float* d_H,
+                        unsigned flags, double* d_energy, void* stream) {
+  if (!p) return fail(DEMAG_EINVAL, "demag_field_noalloc: plan is NULL");
+  if (p->oersted) return fail(DEMAG_EINVAL, "demag_field_noalloc: an Oersted plan");
+  if (p->batch) return fail(DEMAG_EINVAL, "demag_field_noalloc: single-mesh plans only");
+  if (p->work_bytes > (size_t)DEMAG_NOALLOC_WORK_BYTES)
+    return fail(DEMAG_EUNSUPPORTED, "demag_field_noalloc: the plan needs " + std::to_string(p->work_bytes) +
+                                        " bytes of work space, more than the " +
+                                        std::to_string((size_t)DEMAG_NOALLOC_WORK_BYTES) + " of the static scratch");
+  if (!p->bound) return fail(DEMAG_ESTATE, "demag_field_noalloc: plan is not bound");
+  if (!d_m || !d_H) return fail(DEMAG_EINVAL, "demag_field_noalloc: NULL m or H");
+  if (flags & ~(unsigned)DEMAG_ACCUMULATE) return fail(DEMAG_EINVAL, "demag_field_noalloc: unknown flags");
+  if (!d_Ms && !std::isfinite(Ms)) return fail(DEMAG_EINVAL, "demag_field_noalloc: Ms is not finite");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  if (dev != p->device) return fail(DEMAG_EINVAL, "demag_field_noalloc: the current device is not the plan's");
+  return run_field(p, d_m, d_Ms, Ms, nullptr, d_H, flags, d_energy, static_cast<hipStream_t>(stream), nullptr, 0.f,
+                   p->noalloc_work);
 }
 
 int demag_oersted_field(const demag_plan* p, const float* d_J, float scale, float* d_H, unsigned flags,
@@ -1003,6 +1081,7 @@ int demag_oersted_field(const demag_plan* p, const float* d_J, float scale, floa
   if (!p) return fail(DEMAG_EINVAL, "demag_oersted_field: plan is NULL");
   if (!p->oersted) return fail(DEMAG_EINVAL, "demag_oersted_field: not an Oersted plan (use demag_setup_oersted)");
   if (!p->bound) return fail(DEMAG_ESTATE, "demag_oersted_field: plan is not bound");
+  if (!p->has_work) return fail(DEMAG_ESTATE, "demag_oersted_field: plan was bound without a work buffer");
   if (!d_J || !d_H) return fail(DEMAG_EINVAL, "demag_oersted_field: NULL J or H");
   if (flags & ~(unsigned)DEMAG_ACCUMULATE) return fail(DEMAG_EINVAL, "demag_oersted_field: unknown flags");
   if (!std::isfinite(scale)) return fail(DEMAG_EINVAL, "demag_oersted_field: scale is not finite");
@@ -1015,6 +1094,7 @@ int demag_field_2sub(const demag_plan* p, const float* d_mA, const float* d_mB, 
   if (p->oersted) return fail(DEMAG_EINVAL, "demag_field_2sub: an Oersted plan");
   if (p->batch) return fail(DEMAG_EINVAL, "demag_field_2sub: single-mesh plans only");
   if (!p->bound) return fail(DEMAG_ESTATE, "demag_field_2sub: plan is not bound");
+  if (!p->has_work) return fail(DEMAG_ESTATE, "demag_field_2sub: plan was bound without a work buffer");
   if (!d_mA || !d_mB || !d_H) return fail(DEMAG_EINVAL, "demag_field_2sub: NULL mA, mB or H");
   if (flags & ~(unsigned)DEMAG_ACCUMULATE) return fail(DEMAG_EINVAL, "demag_field_2sub: unknown flags");
   if (!std::isfinite(MsA) || !std::isfinite(MsB)) return fail(DEMAG_EINVAL, "demag_field_2sub: Ms is not finite");
@@ -1027,6 +1107,7 @@ int demag_field_batch(const demag_plan* p, const float* d_m, const float* d_Ms_m
   if (!p) return fail(DEMAG_EINVAL, "demag_field_batch: plan is NULL");
   if (!p->batch) return fail(DEMAG_EINVAL, "demag_field_batch: not a batch plan");
   if (!p->bound) return fail(DEMAG_ESTATE, "demag_field_batch: plan is not bound");
+  if (!p->has_work) return fail(DEMAG_ESTATE, "demag_field_batch: plan was bound without a work buffer");
   if (!d_m || !d_H) return fail(DEMAG_EINVAL, "demag_field_batch: NULL m or H");
   if (flags & ~(unsigned)DEMAG_ACCUMULATE) return fail(DEMAG_EINVAL, "demag_field_batch: unknown flags");
   if (!d_Ms_mesh && !std::isfinite(Ms)) return fail(DEMAG_EINVAL, "demag_field_batch: Ms is not finite");
@@ -1042,6 +1123,7 @@ int demag_energy(const demag_plan* p, const float* d_m, const float* d_Ms, float
   if (p->oersted) return fail(DEMAG_EINVAL, "demag_energy: an Oersted plan");
   if (p->batch) return fail(DEMAG_EINVAL, "demag_energy: single-mesh plans only");
   if (!p->bound) return fail(DEMAG_ESTATE, "demag_energy: plan is not bound");
+  if (!p->has_work) return fail(DEMAG_ESTATE, "demag_energy: plan was bound without a work buffer");
   if (!d_m || !d_H || !d_energy) return fail(DEMAG_EINVAL, "demag_energy: NULL argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Sub& sb = p->subs[0];
@@ -1062,6 +1144,7 @@ int demag_backward(const demag_plan* p, const float* d_G, const float* d_Ms, flo
                                             "demag_oersted_field is its own backward)");
   if (p->batch) return fail(DEMAG_EINVAL, "demag_backward: batch plans use demag_backward_batch");
   if (!p->bound) return fail(DEMAG_ESTATE, "demag_backward: plan is not bound");
+  if (!p->has_work) return fail(DEMAG_ESTATE, "demag_backward: plan was bound without a work buffer");
   if (!d_G || !d_grad_m) return fail(DEMAG_EINVAL, "demag_backward: NULL G or grad_m");
   if (d_gE && !d_H) return fail(DEMAG_EINVAL, "demag_backward: the energy term needs the forward field H");
   if (flags & ~(unsigned)DEMAG_ACCUMULATE) return fail(DEMAG_EINVAL, "demag_backward: unknown flags");
@@ -1073,6 +1156,7 @@ int demag_backward_batch(const demag_plan* p, const float* d_G, const float* d_M
   if (!p) return fail(DEMAG_EINVAL, "demag_backward_batch: plan is NULL");
   if (!p->batch) return fail(DEMAG_EINVAL, "demag_backward_batch: not a batch plan");
   if (!p->bound) return fail(DEMAG_ESTATE, "demag_backward_batch: plan is not bound");
+  if (!p->has_work) return fail(DEMAG_ESTATE, "demag_backward_batch: plan was bound without a work buffer");
   if (!d_G || !d_grad_m) return fail(DEMAG_EINVAL, "demag_backward_batch: NULL G or grad_m");
   if (d_gE && !d_H) return fail(DEMAG_EINVAL, "demag_backward_batch: the energy term needs the forward field H");
   if (flags & ~(unsigned)DEMAG_ACCUMULATE) return fail(DEMAG_EINVAL, "demag_backward_batch: unknown flags");
@@ -1163,6 +1247,7 @@ int demag_autotune(demag_plan* p, const float* d_m, float* d_H, const char* cach
       continue;
     }
     if (!p->bound) return fail(DEMAG_ESTATE, "demag_autotune: measuring needs a bound plan");
+    if (!p->has_work) return fail(DEMAG_ESTATE, "demag_autotune: plan was bound without a work buffer");
     if (sub && (!d_m || !d_H)) return fail(DEMAG_EINVAL, "demag_autotune: measuring needs m and H buffers");
     TuneEntry t;
     const int rc = sub ? tune_sub(p, p->subs[i], d_m, d_H, s, t) : tune_group(p, p->groups[i - p->subs.size()], s, t);
@@ -1190,6 +1275,7 @@ int demag_llg_rk4(const demag_plan* p, float* d_m, const demag_llg_params* prm, 
   if (p->oersted) return fail(DEMAG_EINVAL, "demag_llg_rk4: an Oersted plan");
   if (p->batch) return fail(DEMAG_EINVAL, "demag_llg_rk4: single-mesh plans only");
   if (!p->bound) return fail(DEMAG_ESTATE, "demag_llg_rk4: plan is not bound");
+  if (!p->has_work) return fail(DEMAG_ESTATE, "demag_llg_rk4: plan was bound without a work buffer");
   if (!aligned(d_work)) return fail(DEMAG_EINVAL, "demag_llg_rk4: workspace must be 256-byte aligned");
   const float vals[8] = {prm->Ms, prm->A, prm->alpha, prm->gamma, prm->dt, prm->Hext[0], prm->Hext[1], prm->Hext[2]};
   for (float v : vals)

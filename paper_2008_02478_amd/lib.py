@@ -9,6 +9,7 @@ LIB_PATH = os.environ.get("DEMAG_LIB") or os.path.join(os.path.dirname(os.path.a
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
 PBC_X, PBC_Y, PBC_Z = 1, 2, 4
 ACCUMULATE = 1
+NOALLOC_WORK_BYTES = 64 << 20
 TUNE_FORCE = 1
 
 _NAMES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOMEM: "ENOMEM", EHIP: "EHIP", ESTATE: "ESTATE"}
@@ -29,6 +30,7 @@ _SIGS = {
     "demag_buffer_bytes": [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
     "demag_bind": [_vp, _vp, _vp, _vp],
     "demag_field": [_vp, _vp, _vp, _flt, _vp, _uint, _vp, _vp],
+    "demag_field_noalloc": [_vp, _vp, _vp, _flt, _vp, _uint, _vp, _vp],
     "demag_energy": [_vp, _vp, _vp, _flt, _vp, _vp, _vp],
     "demag_backward": [_vp, _vp, _vp, _flt, _vp, _vp, _vp, _uint, _vp],
     "demag_set_timing_events": [_vp, ctypes.POINTER(_vp), _int],

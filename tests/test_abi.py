@@ -426,3 +426,34 @@ def test_xpass_classes_skipped_on_the_gpu_are_rejected_for_every_mesh(lib):
                 if padded(x) == 1 << a and padded(z) == 1 << b:
                     assert not ok(x, ny, z), (a, b, x, z)
     assert n_acc >= 70
+
+
+def test_noalloc_host_checks(lib):
+    p = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(256)
+    # work space beyond the static scratch: refused before the bind state
+    assert lib.demag_setup(ctypes.byref(p), 512, 512, 16, 2e-9, 2e-9, 1e-9, 0, 0) == L.OK
+    try:
+        kb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        assert lib.demag_buffer_bytes(p, ctypes.byref(kb), ctypes.byref(wb)) == L.OK
+        assert wb.value > L.NOALLOC_WORK_BYTES
+        assert lib.demag_field_noalloc(p, dummy, None, 1.0, dummy, 0, None, None) == L.EUNSUPPORTED
+        assert b"static scratch" in lib.demag_last_error()
+    finally:
+        lib.demag_destroy(p)
+    assert lib.demag_setup(ctypes.byref(p), 64, 48, 3, 5e-9, 5e-9, 3e-9, 0, 0) == L.OK
+    try:
+        assert lib.demag_field_noalloc(p, dummy, None, 1.0, dummy, 0, None, None) == L.ESTATE
+        assert lib.demag_bind(p, None, None, None) == L.EINVAL
+    finally:
+        lib.demag_destroy(p)
+    assert lib.demag_field_noalloc(None, dummy, None, 1.0, dummy, 0, None, None) == L.EINVAL
+    dims = (ctypes.c_int * 6)(8, 8, 1, 4, 4, 2)
+    cells = (ctypes.c_double * 6)(1e-9, 1e-9, 1e-9, 1e-9, 1e-9, 1e-9)
+    assert lib.demag_setup_batch(ctypes.byref(p), 2, dims, cells, None, None, 0, 0) == L.OK
+    try:
+        assert lib.demag_field_noalloc(p, dummy, None, 1.0, dummy, 0, None, None) == L.EINVAL
+        # batch plans always need their work buffer
+        assert lib.demag_bind(p, dummy, None, None) == L.EINVAL
+    finally:
+        lib.demag_destroy(p)
