@@ -24,10 +24,10 @@
  *    plan share its work buffer and must be ordered on one stream.
  *  - Arrays of vectors are SoA [3][nz][ny][nx], x fastest, FP32.  Lengths in
  *    metres, M and H in A/m, energies in joules (FP64).
- *  - Supported sizes: 1 <= nx <= 2048, 1 <= ny <= 1024, 1 <= nz <= 64 (nz > 16
- *    only with nx <= 512, nz > 32 only with nx <= 256); each axis zero-padded
- *    to the next power of two >= 2n-1.  The z rows of one y line must also fit
- *    in 160 KiB of LDS.
+ *  - Supported sizes: 1 <= nx <= 2048, 1 <= ny <= 1024, 1 <= nz <= 256; each
+ *    axis zero-padded to the next power of two >= 2n-1.  Short z lines are
+ *    transformed inside the x passes, long ones by separate z passes
+ *    (demag_set_z_passes).
  *  - Periodic boundaries (Sec. 3, multiple images): along a periodic axis a
  *    (period L_a = n_a h_a) the mesh is repeated pbc_images times on either
  *    side and the field is that of the repeated mesh in its central copy,
@@ -273,6 +273,20 @@ int demag_get_schedule(const demag_plan* plan, int part, int* yg, int* kw, int* 
  * Affects later calls only (graphs captured earlier keep their launches);
  * not safe against concurrent calls on the same plan. */
 int demag_set_schedule(demag_plan* plan, int part, int yg, int kw, int radix);
+
+/* How a part transforms along z (Sec. 7: the z transform fused with the
+ * passes around it, the paper's pipelined form, pays for short z lines; long
+ * lines take separate passes).  separate = 0: the z transform runs inside the
+ * x passes (needs the nz rows of a y line in LDS: nz <= 64, nz <= 32 for
+ * nx > 256, nz <= 16 for nx > 512); separate = 1: the x passes run on the
+ * mesh flattened to (nx, ny nz, 1) and two z passes transform the spectrum in
+ * place (2 <= nz <= 256).  demag_setup picks the fused form where it exists;
+ * demag_autotune times both where both exist.  yg of demag_get_schedule /
+ * demag_set_schedule refers to the x passes of the current form.
+ * DEMAG_EUNSUPPORTED for a form the part cannot take (coupled groups have no
+ * z transform); DEMAG_EINVAL for bad arguments.  Host only. */
+int demag_get_z_passes(const demag_plan* plan, int part, int* separate);
+int demag_set_z_passes(demag_plan* plan, int part, int separate);
 
 enum { DEMAG_TUNE_FORCE = 1 };    /* measure even where the cache has an entry */
 

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdemag.so")
-SOURCES = ["k_field.hip", "k_setup.hip", "k_layers.hip", "k_llg.hip", "k_copy.hip", "demag_api.cpp",
+SOURCES = ["k_field.hip", "k_zpass.hip", "k_setup.hip", "k_layers.hip", "k_llg.hip", "k_copy.hip", "demag_api.cpp",
            "tune_cache.cpp"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

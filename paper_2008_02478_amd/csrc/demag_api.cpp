@@ -165,6 +165,18 @@ void gauss_legendre(int n, double* x, double* w) {
 
 bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255) == 0; }
 
+constexpr size_t XTAB_BYTES = 8192;   // stage twiddle table of the x passes (upper bound)
+
+// Whether the fused x+z passes support a geometry: the nz rows of one y line
+// fit in LDS, and the z lines fit the in-register transforms (padded length
+// 64 for nx <= 512, 128 for nx <= 256).
+bool fused_ok(const Geom& g) {
+  if (g.nz > 64 || (g.nz > 16 && g.nx > 512) || (g.nz > 32 && g.nx > 256)) return false;
+  return (size_t)g.nz * xrow_pitch_rt(g.lnx) * sizeof(float2) + XTAB_BYTES <= 160 * 1024;
+}
+// Separate z passes exist for padded z lengths 4..512.
+bool zsep_ok(const Geom& g) { return g.nz >= 2 && g.Nz <= 512; }
+
 // Validate one mesh and derive its geometry (host only).
 constexpr int DEFAULT_IMAGES = 10;
 constexpr int MAX_IMAGES = 1000;
@@ -174,10 +186,8 @@ int make_geom(int nx, int ny, int nz, double dx, double dy, double dz, unsigned 
   if (nx < 1 || ny < 1 || nz < 1) return fail(DEMAG_EINVAL, std::string(who) + ": mesh dimensions must be >= 1");
   if (!(std::isfinite(dx) && std::isfinite(dy) && std::isfinite(dz)) || dx <= 0 || dy <= 0 || dz <= 0)
     return fail(DEMAG_EINVAL, std::string(who) + ": cell sizes must be finite and > 0");
-  if (nx > 2048 || ny > 1024 || nz > 64)
-    return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": supported sizes are nx <= 2048, ny <= 1024, nz <= 64");
-  if ((nz > 16 && nx > 512) || (nz > 32 && nx > 256))
-    return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": nz > 16 needs nx <= 512, nz > 32 needs nx <= 256");
+  if (nx > 2048 || ny > 1024 || nz > 256)
+    return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": supported sizes are nx <= 2048, ny <= 1024, nz <= 256");
   g = Geom{};
   g.nx = nx; g.ny = ny; g.nz = nz;
   g.Nx = padded(nx); g.Ny = padded(ny); g.Nz = padded(nz);
@@ -188,19 +198,23 @@ int make_geom(int nx, int ny, int nz, double dx, double dy, double dz, unsigned 
   g.Kyp = kernel_row_pitch(g.Ny);
   g.nTiles = (g.Kx + TILE - 1) / TILE;
   g.dx = dx; g.dy = dy; g.dz = dz;
-  const size_t pitch_bytes = (size_t)xrow_pitch_rt(g.lnx) * sizeof(float2);
-  const size_t tab_bytes = 8192;   // stage twiddle table of the x passes (upper bound)
-  if ((size_t)nz * pitch_bytes + tab_bytes > 160 * 1024)
-    return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": the nz rows of one y line must fit in 160 KiB of LDS");
   // y rows per workgroup of the x passes: enough rows for one round of the
-  // workgroup, within 64 KiB of LDS
+  // workgroup, within 64 KiB of LDS; for the fused x+z passes a y row brings
+  // its nz rows, for the flattened x passes of separate z passes one row
+  const size_t pitch_bytes = (size_t)xrow_pitch_rt(g.lnx) * sizeof(float2);
   const int P = g.Nx >= 4 ? g.Nx / 4 : 1;
   const int rpr = FWD_THREADS / (2 * line_threads(P));
-  int yg = (rpr + nz - 1) / nz;
-  while (yg > 1 && (size_t)yg * nz * pitch_bytes + tab_bytes > 65536) --yg;
-  if (yg > ny) yg = ny;
-  if (yg < 1) yg = 1;
-  g.yg = yg;
+  auto rows_per_wg = [&](int zrows, int nrows) {
+    int yg = (rpr + zrows - 1) / zrows;
+    while (yg > 1 && (size_t)yg * zrows * pitch_bytes + XTAB_BYTES > 65536) --yg;
+    if (yg > nrows) yg = nrows;
+    return yg < 1 ? 1 : yg;
+  };
+  g.yg = rows_per_wg(nz, ny);
+  g.yg_sep = rows_per_wg(1, ny * nz);
+  // the fused x+z passes need the nz rows of a y line in LDS and their z
+  // lines in registers; beyond that the z transform runs as separate passes
+  g.zsep = fused_ok(g) ? 0 : 1;
   g.mid_kw = 4;
   g.mid_r = 0;
   g.pbc = pbc;
@@ -313,6 +327,8 @@ int make_group(const std::vector<int>& idx, const int* dims, const double* cells
   g.nTiles = (g.Kx + TILE - 1) / TILE;
   g.dx = fx; g.dy = fy; g.dz = 1.0;
   g.yg = 1;
+  g.zsep = 0;
+  g.yg_sep = 1;
   g.mid_kw = 4;
   g.mid_r = 0;
   g.pbc = 0;
@@ -539,12 +555,51 @@ Slab slab_of(const Sub& sb, char* base) {
   return Slab{reinterpret_cast<float2*>(base + sb.t_off), reinterpret_cast<double*>(base + sb.e_off)};
 }
 
+// Geometry the x passes run on: the mesh itself (fused x+z passes), or with
+// separate z passes the mesh flattened to (nx, ny nz, 1) rows.
+Geom xgeom(const Geom& g) {
+  if (!g.zsep) return g;
+  Geom f = g;
+  f.ny = g.ny * g.nz;
+  f.nz = 1; f.Nz = 1; f.lnz = 0; f.Kzh = 1;
+  f.yg = g.yg_sep;
+  f.zsep = 0;
+  return f;
+}
+
 FwdArgs fwd_args(const demag_plan* p, const Sub& sb, const float* src, const float* Ms, float ms,
                  const float* ms_mesh, const float* src2 = nullptr, float ms2 = 0.f, char* base = nullptr) {
   const Geom& g = sb.g;
-  return FwdArgs{src, Ms, ms, slab_of(sb, base).T, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, (int)sb.members.size(),
-                 p->batch ? sb.moff : nullptr, ms_mesh, spectrum_elems(g), p->batch ? sb.gid : nullptr,
-                 src2, ms2};
+  const Geom x = xgeom(g);
+  FwdArgs a{src, Ms, ms, slab_of(sb, base).T, p->tw, x.nx, x.ny, x.nz, x.nTiles, x.Kx, x.yg,
+            (int)sb.members.size(), p->batch ? sb.moff : nullptr, ms_mesh, spectrum_elems(g),
+            p->batch ? sb.gid : nullptr, src2, ms2};
+  a.ysplit = g.zsep ? g.ny : 0;
+  a.nzp = g.Nz;
+  return a;
+}
+
+ZArgs z_args(const demag_plan* p, const Sub& sb, char* base = nullptr) {
+  const Geom& g = sb.g;
+  return ZArgs{slab_of(sb, base).T, p->tw, g.ny, g.nz, g.nTiles, (int)sb.members.size(), spectrum_elems(g)};
+}
+
+// The inverse x pass (after the inverse z pass of separate z passes).
+int run_inv(const demag_plan* p, const Sub& sb, InvArgs ia, hipStream_t s, char* base = nullptr) {
+  const Geom& g = sb.g;
+  hipError_t e = hipSuccess;
+  if (g.zsep) {
+    e = launch_zpass(g.lnz, z_args(p, sb, base), true, s);
+    if (e != hipSuccess) return fail_hip(e, "inverse z pass");
+    const Geom x = xgeom(g);
+    ia.ny = x.ny; ia.nz = 1; ia.yg = x.yg;
+    ia.ysplit = g.ny;
+    ia.nzp = g.Nz;
+    e = launch_inv(x, ia, s);
+  } else {
+    e = launch_inv(g, ia, s);
+  }
+  return e == hipSuccess ? DEMAG_OK : fail_hip(e, "inverse pass");
 }
 
 MidArgs mid_args(const demag_plan* p, const Sub& sb, bool energy, char* base = nullptr) {
@@ -561,8 +616,12 @@ int run_conv(const demag_plan* p, const Sub& sb, const float* src, const float* 
   const Geom& g = sb.g;
   int rc = mark(p, 0, s);
   if (rc != DEMAG_OK) return rc;
-  hipError_t e = launch_fwd(g, fwd_args(p, sb, src, Ms, ms, ms_mesh, src2, ms2, base), s);
+  hipError_t e = launch_fwd(xgeom(g), fwd_args(p, sb, src, Ms, ms, ms_mesh, src2, ms2, base), s);
   if (e != hipSuccess) return fail_hip(e, "forward pass");
+  if (g.zsep) {
+    e = launch_zpass(g.lnz, z_args(p, sb, base), false, s);
+    if (e != hipSuccess) return fail_hip(e, "forward z pass");
+  }
   if ((rc = mark(p, 1, s)) != DEMAG_OK) return rc;
   e = launch_mid(g, mid_args(p, sb, energy, base), s);
   if (e != hipSuccess) return fail_hip(e, "middle pass");
@@ -583,12 +642,11 @@ int run_field(const demag_plan* p, const float* d_m, const float* d_Ms, float Ms
     InvArgs ia{w.T, d_H, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, (flags & DEMAG_ACCUMULATE) ? 1 : 0,
                nullptr, nullptr, 0.0, nullptr, 0.f, 0,
                nb, p->batch ? sb.moff : nullptr, ms_mesh, spectrum_elems(g), p->batch ? sb.gid : nullptr};
-    hipError_t e = launch_inv(g, ia, s);
-    if (e != hipSuccess) return fail_hip(e, "inverse pass");
+    if ((rc = run_inv(p, sb, ia, s, base)) != DEMAG_OK) return rc;
     if ((rc = mark(p, 3, s)) != DEMAG_OK) return rc;
     if (d_energy) {
       const double V = g.dx * g.dy * g.dz;
-      e = launch_energy_final(w.epart, mid_blocks(g), -0.5 * MU0 * V, d_energy, s, nb, p->batch ? sb.gid : nullptr);
+      const hipError_t e = launch_energy_final(w.epart, mid_blocks(g), -0.5 * MU0 * V, d_energy, s, nb, p->batch ? sb.gid : nullptr);
       if (e != hipSuccess) return fail_hip(e, "energy reduction");
     }
   }
@@ -606,8 +664,7 @@ int run_backward(const demag_plan* p, const float* d_G, const float* d_Ms, float
     InvArgs ia{sb.T, d_grad, p->tw, g.nx, g.ny, g.nz, g.nTiles, g.Kx, g.yg, (flags & DEMAG_ACCUMULATE) ? 1 : 0,
                d_H, d_gE, -MU0 * V, d_Ms, Ms, 1,
                nb, p->batch ? sb.moff : nullptr, ms_mesh, spectrum_elems(g), p->batch ? sb.gid : nullptr};
-    hipError_t e = launch_inv(g, ia, s);
-    if (e != hipSuccess) return fail_hip(e, "inverse pass");
+    if ((rc = run_inv(p, sb, ia, s)) != DEMAG_OK) return rc;
     if ((rc = mark(p, 3, s)) != DEMAG_OK) return rc;
   }
   return DEMAG_OK;
@@ -628,9 +685,16 @@ Geom& part_geom(demag_plan* p, int i) {
   return i < (int)p->subs.size() ? p->subs[i].g : p->groups[i - p->subs.size()].g;
 }
 
+// y rows per workgroup of the active x passes (fused: y lines of nz rows;
+// separate z passes: rows of the flattened mesh)
+int& active_yg(Geom& g) { return g.zsep ? g.yg_sep : g.yg; }
+int active_yg(const Geom& g) { return g.zsep ? g.yg_sep : g.yg; }
+
 bool yg_ok(const Geom& g, int yg) {
-  if (yg < 1 || yg > g.ny) return false;
-  return (size_t)yg * g.nz * xrow_pitch_rt(g.lnx) * sizeof(float2) + 8192 <= 160 * 1024;
+  const int rows = g.zsep ? g.ny * g.nz : g.ny;
+  const int zr = g.zsep ? 1 : g.nz;
+  if (yg < 1 || yg > rows) return false;
+  return (size_t)yg * zr * xrow_pitch_rt(g.lnx) * sizeof(float2) + XTAB_BYTES <= 160 * 1024;
 }
 
 bool kw_ok(int kw) { return kw == 2 || kw == 4 || kw == 8; }
@@ -710,22 +774,53 @@ int time_calls(hipStream_t s, F&& fn, double& us) {
 // Measure the candidates of sub-plan sb and keep the fastest in its geometry.
 int tune_sub(demag_plan* p, Sub& sb, const float* d_m, float* d_H, hipStream_t s, TuneEntry& out) {
   Geom& g = sb.g;
-  const int d = g.yg;
+  // one field sequence without energy: forward x (and z) passes, middle
+  // pass, inverse (z and) x passes
+  auto sequence = [&]() -> int {
+    hipError_t e = launch_fwd(xgeom(g), fwd_args(p, sb, d_m, nullptr, 1.0f, nullptr), s);
+    if (e == hipSuccess && g.zsep) e = launch_zpass(g.lnz, z_args(p, sb), false, s);
+    if (e == hipSuccess) e = launch_mid(g, mid_args(p, sb, false), s);
+    if (e != hipSuccess) return fail_hip(e, "field sequence");
+    return run_inv(p, sb, inv_plain_args(p, sb, d_H, 0u, nullptr), s);
+  };
+  // fused x+z passes or separate z passes, where both exist
+  if (fused_ok(g) && zsep_ok(g)) {
+    const int z0 = g.zsep;
+    double t[2] = {0.0, 0.0};
+    for (int z = 0; z < 2; ++z) {
+      g.zsep = z;
+      const int rc = time_calls(s, sequence, t[z]);
+      if (rc != DEMAG_OK) {
+        g.zsep = z0;
+        return rc;
+      }
+    }
+    g.zsep = t[1] < t[0] ? 1 : 0;
+  }
+  out.zsep = g.zsep;
+  const int d = active_yg(g);
   std::vector<int> ygs;
   for (int c : {d / 2, d, 2 * d, 4 * d})
     if (yg_ok(g, c) && std::find(ygs.begin(), ygs.end(), c) == ygs.end()) ygs.push_back(c);
   double best = 1e300;
   int best_yg = d;
   for (int yg : ygs) {
-    g.yg = yg;
+    active_yg(g) = yg;
     double us = 0.0;
     const int rc = time_calls(s, [&]() -> int {
-      hipError_t e = launch_fwd(g, fwd_args(p, sb, d_m, nullptr, 1.0f, nullptr), s);
-      if (e == hipSuccess) e = launch_inv(g, inv_plain_args(p, sb, d_H, 0u, nullptr), s);
+      const Geom x = xgeom(g);
+      hipError_t e = launch_fwd(x, fwd_args(p, sb, d_m, nullptr, 1.0f, nullptr), s);
+      if (e == hipSuccess) {
+        InvArgs ia = inv_plain_args(p, sb, d_H, 0u, nullptr);
+        ia.ny = x.ny; ia.nz = x.nz; ia.yg = x.yg;
+        ia.ysplit = g.zsep ? g.ny : 0;
+        ia.nzp = g.Nz;
+        e = launch_inv(x, ia, s);
+      }
       return e == hipSuccess ? DEMAG_OK : fail_hip(e, "x passes");
     }, us);
     if (rc != DEMAG_OK) {
-      g.yg = d;
+      active_yg(g) = d;
       return rc;
     }
     if (us < best) {
@@ -733,7 +828,7 @@ int tune_sub(demag_plan* p, Sub& sb, const float* d_m, float* d_H, hipStream_t s
       best_yg = yg;
     }
   }
-  g.yg = best_yg;
+  active_yg(g) = best_yg;
   out.yg = best_yg;
   out.x_us = best;
   const int kw0 = g.mid_kw, r0 = g.mid_r;
@@ -747,12 +842,7 @@ int tune_sub(demag_plan* p, Sub& sb, const float* d_m, float* d_H, hipStream_t s
       // timed inside the whole field sequence: alone, the middle pass can
       // rank its candidates differently (cache state, clocks)
       double us = 0.0;
-      const int rc = time_calls(s, [&]() -> int {
-        hipError_t e = launch_fwd(g, fwd_args(p, sb, d_m, nullptr, 1.0f, nullptr), s);
-        if (e == hipSuccess) e = launch_mid(g, mid_args(p, sb, false), s);
-        if (e == hipSuccess) e = launch_inv(g, inv_plain_args(p, sb, d_H, 0u, nullptr), s);
-        return e == hipSuccess ? DEMAG_OK : fail_hip(e, "field sequence");
-      }, us);
+      const int rc = time_calls(s, sequence, us);
       if (rc != DEMAG_OK) {
         g.mid_kw = kw0;
         g.mid_r = r0;
@@ -1191,9 +1281,30 @@ int demag_get_schedule(const demag_plan* p, int part, int* yg, int* kw, int* rad
   if (!p || !yg || !kw || !radix) return fail(DEMAG_EINVAL, "demag_get_schedule: NULL argument");
   if (part < 0 || part >= part_count(p)) return fail(DEMAG_EINVAL, "demag_get_schedule: part out of range");
   const Geom& g = part_geom(const_cast<demag_plan*>(p), part);
-  *yg = part < (int)p->subs.size() ? g.yg : 0;
+  *yg = part < (int)p->subs.size() ? active_yg(g) : 0;
   *kw = mid_kw(g);
   *radix = mid_radix(g);
+  return DEMAG_OK;
+}
+
+int demag_get_z_passes(const demag_plan* p, int part, int* separate) {
+  if (!p || !separate) return fail(DEMAG_EINVAL, "demag_get_z_passes: NULL argument");
+  if (part < 0 || part >= part_count(p)) return fail(DEMAG_EINVAL, "demag_get_z_passes: part out of range");
+  *separate = part_geom(const_cast<demag_plan*>(p), part).zsep;
+  return DEMAG_OK;
+}
+
+int demag_set_z_passes(demag_plan* p, int part, int separate) {
+  if (!p) return fail(DEMAG_EINVAL, "demag_set_z_passes: plan is NULL");
+  if (part < 0 || part >= part_count(p)) return fail(DEMAG_EINVAL, "demag_set_z_passes: part out of range");
+  if (separate != 0 && separate != 1) return fail(DEMAG_EINVAL, "demag_set_z_passes: separate must be 0 or 1");
+  if (part >= (int)p->subs.size())
+    return fail(DEMAG_EUNSUPPORTED, "demag_set_z_passes: coupled groups have no z transform");
+  Geom& g = part_geom(p, part);
+  if (separate ? !zsep_ok(g) : !fused_ok(g))
+    return fail(DEMAG_EUNSUPPORTED, separate ? "demag_set_z_passes: separate z passes need 2 <= nz <= 256"
+                                             : "demag_set_z_passes: this mesh is too deep for the fused x+z passes");
+  g.zsep = separate;
   return DEMAG_OK;
 }
 
@@ -1210,7 +1321,7 @@ int demag_set_schedule(demag_plan* p, int part, int yg, int kw, int radix) {
     return fail(DEMAG_EUNSUPPORTED, "demag_set_schedule: radix not available for this y length");
   if (!sched_ok(g, kw ? kw : mid_kw(g), radix ? radix : mid_radix(g)))
     return fail(DEMAG_EUNSUPPORTED, "demag_set_schedule: this kw and radix need more than 128 registers per lane");
-  if (yg) g.yg = yg;
+  if (yg) active_yg(g) = yg;
   if (kw) g.mid_kw = kw;
   if (radix) g.mid_r = radix;
   return DEMAG_OK;
@@ -1239,9 +1350,17 @@ int demag_autotune(demag_plan* p, const float* d_m, float* d_H, const char* cach
     if (it != cache.end() && !(flags & DEMAG_TUNE_FORCE)) {
       const TuneEntry& c = it->second;
       Geom& g = part_geom(p, i);
-      if ((sub ? !yg_ok(g, c.yg) : c.yg != 0) || !sched_ok(g, c.kw, c.radix))
+      const int z0 = g.zsep;
+      if (c.zsep >= 0) {
+        if (!sub || c.zsep > 1 || (c.zsep ? !zsep_ok(g) : !fused_ok(g)))
+          return fail(DEMAG_EINVAL, "demag_autotune: cache entry '" + key + "' holds an unsupported z mode");
+        g.zsep = c.zsep;
+      }
+      if ((sub ? !yg_ok(g, c.yg) : c.yg != 0) || !sched_ok(g, c.kw, c.radix)) {
+        g.zsep = z0;
         return fail(DEMAG_EINVAL, "demag_autotune: cache entry '" + key + "' holds an unsupported schedule");
-      if (sub) g.yg = c.yg;
+      }
+      if (sub) active_yg(g) = c.yg;
       g.mid_kw = c.kw;
       g.mid_r = c.radix;
       continue;

@@ -102,7 +102,15 @@ __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_e
     const int yl = it / Kx, kx = it - yl * Kx;
     const unsigned o = ((unsigned)(kx / TILE) * ny + (y0 + yl)) * TILE + (kx % TILE);
     if constexpr (NZ == 1) {
-      Tc[o] = smem[(yl * nz) * PITCH + kx];
+      if (a.ysplit) {
+        // flattened rows: plane z = y' / ysplit of nzp per component
+        const int yy = y0 + yl, zz = yy / a.ysplit, yr = yy - zz * a.ysplit;
+        const size_t psz = (size_t)a.nTiles * a.ysplit * TILE;
+        a.T[((size_t)c * a.nzp + zz) * psz + ((size_t)(kx / TILE) * a.ysplit + yr) * TILE + (kx % TILE)] =
+            smem[(yl * nz) * PITCH + kx];
+      } else {
+        Tc[o] = smem[(yl * nz) * PITCH + kx];
+      }
     } else {
       constexpr int Q = NZ / 2;
       if constexpr (NZ >= 128) {
@@ -537,7 +545,13 @@ __global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_e
     const unsigned o = ((unsigned)(kx / TILE) * ny + (y0 + yl)) * TILE + (kx % TILE);
     float2* const d0 = &smem[(yl * nz) * PITCH + kx];
     if constexpr (NZ == 1) {
-      d0[0] = Tc[o];
+      if (a.ysplit) {
+        const int yy = y0 + yl, zz = yy / a.ysplit, yr = yy - zz * a.ysplit;
+        const size_t psz = (size_t)a.nTiles * a.ysplit * TILE;
+        d0[0] = a.T[((size_t)c * a.nzp + zz) * psz + ((size_t)(kx / TILE) * a.ysplit + yr) * TILE + (kx % TILE)];
+      } else {
+        d0[0] = Tc[o];
+      }
     } else {
       constexpr int Q = NZ / 2;
       // both residues requested before either is transformed (one at a time

@@ -7,6 +7,7 @@ namespace demag {
 
 hipError_t launch_fwd(const Geom& g, const FwdArgs& a, hipStream_t s);
 hipError_t launch_mid(const Geom& g, const MidArgs& a, hipStream_t s);
+hipError_t launch_zpass(int lnz, const ZArgs& a, bool inverse, hipStream_t s);
 hipError_t launch_inv(const Geom& g, const InvArgs& a, hipStream_t s);
 hipError_t launch_energy_final(const double* part, int n, double scale, double* out, hipStream_t s, int nb = 1,
                                const int* gid = nullptr);

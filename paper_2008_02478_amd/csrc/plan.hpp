@@ -72,6 +72,8 @@ struct Geom {
   int yg;              // y rows per workgroup in the x passes
   int mid_kw;          // kx lines per workgroup of the middle pass (2, 4 or 8)
   int mid_r;           // points per lane of its y line FFT (0: line_radix)
+  int zsep;            // 1: z transformed by separate passes (x passes on the mesh flattened to ny nz rows)
+  int yg_sep;          // rows per workgroup of those flattened x passes
   unsigned pbc;        // periodic axes (bit 0 x, 1 y, 2 z): image-summed tensor
   int images;          // images K on either side along each periodic axis
   int kind;            // KERNEL_DEMAG or KERNEL_OERSTED
@@ -150,6 +152,10 @@ struct FwdArgs {
   int nb; const long long* moff; const float* ms_mesh; size_t Tb; const int* gid;
   // second sublattice (nullptr: none): the input is (ms m + ms2 m2) / 2
   const float* m2; float ms2;
+  // flattened x pass of a plan with separate z passes (0: off): row y' of the
+  // (nx, ny nz, 1) mesh is spectrum plane z = y' / ysplit, row y' % ysplit, of
+  // nzp planes per component
+  int ysplit; int nzp;
 };
 
 struct MidArgs {
@@ -168,6 +174,14 @@ struct InvArgs {
   // s = per-cell Ms (or the scalar) and beta = beta_scale * beta_ptr[member]
   const float* aux; const double* beta_ptr; double beta_scale; const float* Ms; float ms; int scale_out;
   int nb; const long long* moff; const float* ms_mesh; size_t Tb; const int* gid;
+  int ysplit; int nzp;         // as in FwdArgs
+};
+
+// Separate z passes (k_zpass.hip): in place on the spectrum T of nb members.
+struct ZArgs {
+  float2* T; const float2* tw;
+  int ny, nz, nTiles;
+  int nb; size_t Tb;
 };
 
 // One RK4 stage of the LLG evaluation loop (k_llg.hip).

@@ -113,10 +113,11 @@ struct Reader {
     do {
       std::string k;
       if (!string(k) || !lit(':')) return bad("bad entry");
-      if (k == "yg" || k == "kw" || k == "radix" || k == "x_us" || k == "mid_us") {
+      if (k == "yg" || k == "kw" || k == "radix" || k == "zsep" || k == "x_us" || k == "mid_us") {
         double v;
         if (!number(v)) return false;
         if (k == "yg") e.yg = (int)v;
+        else if (k == "zsep") e.zsep = (int)v;
         else if (k == "kw") e.kw = (int)v;
         else if (k == "radix") e.radix = (int)v;
         else if (k == "x_us") e.x_us = v;
@@ -223,8 +224,9 @@ bool tune_cache_write(const std::string& path, const TuneMap& m, std::string& er
   char buf[256];
   for (const auto& kv : m) {
     const TuneEntry& e = kv.second;
-    std::snprintf(buf, sizeof buf, "{\"yg\": %d, \"kw\": %d, \"radix\": %d, \"x_us\": %.3f, \"mid_us\": %.3f}", e.yg,
-                  e.kw, e.radix, e.x_us, e.mid_us);
+    std::snprintf(buf, sizeof buf,
+                  "{\"yg\": %d, \"kw\": %d, \"radix\": %d, \"zsep\": %d, \"x_us\": %.3f, \"mid_us\": %.3f}", e.yg,
+                  e.kw, e.radix, e.zsep, e.x_us, e.mid_us);
     text += first ? "\n    " : ",\n    ";
     text += quote(kv.first) + ": " + buf;
     first = false;

@@ -3,7 +3,7 @@
 // launch shape and the times that were measured for it.
 //
 //   {"format": "demag-schedule-cache/1",
-//    "entries": {"<key>": {"yg": 2, "kw": 4, "radix": 8, "x_us": 190.0, "mid_us": 230.5}, ...}}
+//    "entries": {"<key>": {"yg": 2, "kw": 4, "radix": 8, "zsep": 0, "x_us": 190.0, "mid_us": 230.5}, ...}}
 //
 // Host code only; no HIP calls.
 #pragma once
@@ -16,6 +16,7 @@ struct TuneEntry {
   int yg = 0;        // y rows per workgroup of the x passes (0: not tuned)
   int kw = 0;        // kx lines per workgroup of the middle pass
   int radix = 0;     // points per lane of its y line FFT
+  int zsep = -1;     // 1: separate z passes, 0: fused x+z passes (-1: not recorded)
   double x_us = 0;   // measured time of the x passes (forward + inverse)
   double mid_us = 0; // measured time of the middle pass(es)
 };

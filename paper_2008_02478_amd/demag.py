@@ -39,6 +39,15 @@ class _Schedules:
     def set_schedule(self, part, yg=0, kw=0, radix=0):
         _l.check(self._lib.demag_set_schedule(self._p, int(part), int(yg), int(kw), int(radix)))
 
+    def z_passes(self, part=0):
+        """True when the part transforms along z in separate passes."""
+        v = ctypes.c_int()
+        _l.check(self._lib.demag_get_z_passes(self._p, int(part), ctypes.byref(v)))
+        return bool(v.value)
+
+    def set_z_passes(self, separate, part=0):
+        _l.check(self._lib.demag_set_z_passes(self._p, int(part), int(bool(separate))))
+
     def autotune(self, cache=None, force=False):
         """Pick each part's launch schedule by timing the candidates on the
         current stream (or from the JSON cache file `cache`, which is updated

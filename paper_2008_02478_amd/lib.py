@@ -43,6 +43,8 @@ _SIGS = {
     "demag_schedule_count": [_vp, ctypes.POINTER(_int)],
     "demag_get_schedule": [_vp, _int, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int)],
     "demag_set_schedule": [_vp, _int, _int, _int, _int],
+    "demag_get_z_passes": [_vp, _int, ctypes.POINTER(_int)],
+    "demag_set_z_passes": [_vp, _int, _int],
     "demag_autotune": [_vp, _vp, _vp, ctypes.c_char_p, _uint, ctypes.POINTER(_int), _vp],
     "demag_field_2sub": [_vp, _vp, _vp, _flt, _flt, _vp, _uint, _vp, _vp],
     "demag_llg_workspace_bytes": [_vp, ctypes.POINTER(ctypes.c_size_t)],

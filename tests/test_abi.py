@@ -46,12 +46,9 @@ def setup(lib, *args):
     ((4, 4, 4, 1e-9, 1e-9, float("inf"), 0, 0), L.EINVAL),
     ((4, 4, 4, 1e-9, 1e-9, 1e-9, 8, 0), L.EINVAL),
     ((4, 4, 4, 1e-9, 1e-9, 1e-9, L.PBC_X, 1001), L.EINVAL),
-    ((4, 4, 65, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
-    ((300, 4, 33, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
-    ((600, 4, 17, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
+    ((4, 4, 257, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
     ((4, 1025, 4, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
     ((2049, 4, 4, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
-    ((2048, 4, 16, 1e-9, 1e-9, 1e-9, 0, 0), L.EUNSUPPORTED),
 ])
 def test_setup_rejects(lib, args, code):
     rc, p = setup(lib, *args)
@@ -145,7 +142,7 @@ def test_batch_setup_and_layout(lib):
 
 @pytest.mark.parametrize("n,code", [(0, L.EINVAL), (2, L.EUNSUPPORTED)])
 def test_batch_setup_rejects(lib, n, code):
-    dims = (ctypes.c_int * 6)(4, 3, 2, 4, 3, 65)
+    dims = (ctypes.c_int * 6)(4, 3, 2, 4, 3, 257)
     cells = (ctypes.c_double * 6)(1e-9, 1e-9, 1e-9, 1e-9, 1e-9, 1e-9)
     p = ctypes.c_void_p()
     assert lib.demag_setup_batch(ctypes.byref(p), n, dims, cells, None, None, 0, 0) == code
@@ -335,7 +332,7 @@ def test_oersted_plan_host_checks(lib):
     assert lib.demag_setup_oersted(None, 8, 8, 1, 1e-9, 1e-9, 1e-9, 0, 0) == L.EINVAL
     assert lib.demag_setup_oersted(ctypes.byref(p), 0, 8, 1, 1e-9, 1e-9, 1e-9, 0, 0) == L.EINVAL
     assert lib.demag_setup_oersted(ctypes.byref(p), 8, 8, 1, 1e-9, -1e-9, 1e-9, 0, 0) == L.EINVAL
-    assert lib.demag_setup_oersted(ctypes.byref(p), 8, 8, 65, 1e-9, 1e-9, 1e-9, 0, 0) == L.EUNSUPPORTED
+    assert lib.demag_setup_oersted(ctypes.byref(p), 8, 8, 257, 1e-9, 1e-9, 1e-9, 0, 0) == L.EUNSUPPORTED
     assert lib.demag_setup_oersted(ctypes.byref(p), 8, 8, 1, 1e-9, 1e-9, 1e-9, 8, 0) == L.EINVAL
     assert lib.demag_setup_oersted(ctypes.byref(p), 8, 8, 1, 1e-9, 1e-9, 1e-9, L.PBC_X, 1001) == L.EINVAL
     assert lib.demag_setup_oersted(ctypes.byref(p), 8, 8, 1, 1e-9, 1e-9, 1e-9, L.PBC_X | L.PBC_Y, 0) == L.OK
@@ -455,5 +452,53 @@ def test_noalloc_host_checks(lib):
         assert lib.demag_field_noalloc(p, dummy, None, 1.0, dummy, 0, None, None) == L.EINVAL
         # batch plans always need their work buffer
         assert lib.demag_bind(p, dummy, None, None) == L.EINVAL
+    finally:
+        lib.demag_destroy(p)
+
+
+@pytest.mark.parametrize("n,fused,separate", [
+    ((4, 4, 1), True, False),        # no z transform at all
+    ((512, 512, 16), True, True),
+    ((256, 256, 64), True, True),
+    ((4, 4, 65), False, True),
+    ((300, 4, 33), False, True),
+    ((600, 4, 17), False, True),
+    ((2048, 4, 16), False, True),    # the 16 rows of a y line exceed LDS
+    ((1024, 1024, 32), False, True),
+    ((8, 8, 256), False, True),
+])
+def test_z_pass_forms(lib, n, fused, separate):
+    rc, p = setup(lib, *n, 2e-9, 2e-9, 1e-9, 0, 0)
+    assert rc == L.OK
+    try:
+        v = ctypes.c_int()
+        assert lib.demag_get_z_passes(p, 0, ctypes.byref(v)) == L.OK
+        assert v.value == (0 if fused else 1)        # the fused form wherever it exists
+        assert lib.demag_set_z_passes(p, 0, 1) == (L.OK if separate else L.EUNSUPPORTED)
+        assert lib.demag_set_z_passes(p, 0, 0) == (L.OK if fused else L.EUNSUPPORTED)
+        assert lib.demag_set_z_passes(p, 0, 2) == L.EINVAL
+        assert lib.demag_set_z_passes(p, 1, 0) == L.EINVAL
+        assert lib.demag_get_z_passes(p, 0, None) == L.EINVAL
+        # yg of the schedule follows the form: flattened rows with separate z passes
+        if separate:
+            assert lib.demag_set_z_passes(p, 0, 1) == L.OK
+            yg = ctypes.c_int()
+            kw, r = ctypes.c_int(), ctypes.c_int()
+            assert lib.demag_get_schedule(p, 0, ctypes.byref(yg), ctypes.byref(kw), ctypes.byref(r)) == L.OK
+            assert 1 <= yg.value <= n[1] * n[2]
+            assert lib.demag_set_schedule(p, 0, n[1] * n[2] + 1, 0, 0) == L.EINVAL
+    finally:
+        lib.demag_destroy(p)
+
+
+def test_z_passes_refused_for_coupled_groups(lib):
+    dims = (ctypes.c_int * 6)(8, 8, 1, 8, 8, 1)
+    cells = (ctypes.c_double * 6)(1e-9, 1e-9, 1e-9, 1e-9, 1e-9, 1e-9)
+    origin = (ctypes.c_double * 6)(0, 0, 0, 0, 0, 2e-9)
+    group = (ctypes.c_int * 2)(0, 0)
+    p = ctypes.c_void_p()
+    assert lib.demag_setup_batch(ctypes.byref(p), 2, dims, cells, origin, group, 0, 0) == L.OK
+    try:
+        assert lib.demag_set_z_passes(p, 0, 1) == L.EUNSUPPORTED
     finally:
         lib.demag_destroy(p)
