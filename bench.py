@@ -39,6 +39,13 @@ WORKLOADS = {
     "256x128x4": dict(n=(256, 128, 4), h=(5e-9, 5e-9, 2e-9), Ms=8e5, seed=4),
     "256x256x64": dict(n=(256, 256, 64), h=(4e-9, 4e-9, 4e-9), Ms=8e5, seed=12),
     "64x64x1": dict(n=(64, 64, 1), h=(5e-9, 5e-9, 3e-9), Ms=8e5, seed=1),
+    # z-form crossover (fused x+z passes vs separate z passes) and deep meshes
+    "256x256x4": dict(n=(256, 256, 4), h=(4e-9, 4e-9, 4e-9), Ms=8e5, seed=13),
+    "256x256x16": dict(n=(256, 256, 16), h=(4e-9, 4e-9, 4e-9), Ms=8e5, seed=14),
+    "256x256x32": dict(n=(256, 256, 32), h=(4e-9, 4e-9, 4e-9), Ms=8e5, seed=15),
+    "256x256x128": dict(n=(256, 256, 128), h=(4e-9, 4e-9, 4e-9), Ms=8e5, seed=16),
+    "512x512x32": dict(n=(512, 512, 32), h=(2e-9, 2e-9, 1e-9), Ms=1.1e6, seed=17),
+    "1024x1024x32": dict(n=(1024, 1024, 32), h=(2e-9, 2e-9, 1e-9), Ms=1.1e6, seed=18),
 }
 
 
@@ -311,6 +318,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch schedules")
     ap.add_argument("--schedule-cache", default=None, help="JSON schedule cache to apply (and extend)")
+    ap.add_argument("--z-form", choices=("auto", "fused", "separate"), default="auto",
+                    help="z transform inside the x passes (fused) or in separate passes; auto: the tuner's choice")
     ap.add_argument("--main-only", action="store_true",
                     help="time the field + backward step only (no batch, RK4 or Oersted legs), e.g. under a profiler")
     args = ap.parse_args()
@@ -330,7 +339,7 @@ def main():
     ncell = n[0] * n[1] * n[2]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.workload in ("512x512x16", "1024x1024x4"):
+    if h == (2e-9, 2e-9, 1e-9):
         m_np = inputs.voronoi(n, (h[0] * 1e9, h[1] * 1e9, h[2] * 1e9), seed=wl["seed"])
     else:
         m_np = inputs.unit_sphere(n, seed=wl["seed"])
@@ -339,9 +348,11 @@ def main():
     plan = DemagPlan(n, h, device=dev)
     torch.cuda.synchronize()
     setup_s = time.time() - t0
+    if args.z_form != "auto":
+        plan.set_z_passes(args.z_form == "separate")
     t0 = time.time()
     if not args.no_tune:
-        plan.autotune(cache=args.schedule_cache)
+        plan.autotune(cache=args.schedule_cache, keep_form=args.z_form != "auto")
     tune_s = time.time() - t0
     m = torch.from_numpy(m_np).to(dev)
     G = torch.from_numpy(G_np).to(dev)
@@ -442,6 +453,7 @@ def main():
         "setup_s": setup_s,
         "tune_s": tune_s,
         "schedule": plan.schedules()[0],
+        "z_form": "separate" if plan.z_passes() else "fused",
         "roofline": {
             "bound": "hbm",
             "kernel": "k_mid (y FFT + kernel product + inverse y FFT)",

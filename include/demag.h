@@ -288,13 +288,16 @@ int demag_set_schedule(demag_plan* plan, int part, int yg, int kw, int radix);
 int demag_get_z_passes(const demag_plan* plan, int part, int* separate);
 int demag_set_z_passes(demag_plan* plan, int part, int separate);
 
-enum { DEMAG_TUNE_FORCE = 1 };    /* measure even where the cache has an entry */
+enum { DEMAG_TUNE_FORCE = 1,      /* measure even where the cache has an entry */
+       DEMAG_TUNE_KEEP_FORM = 2 }; /* keep each part's current z form (fused or separate) */
 
 /* Launch-shape tuner.  For each part: if cache_path names a schedule cache
  * (JSON, "demag-schedule-cache/1") holding an entry for this device and
  * geometry, apply it; else time every candidate schedule on `stream` with
- * HIP events (x passes over the yg candidates, then the whole field sequence
- * over the middle pass's kw x radix), keep the fastest and, when cache_path
+ * HIP events (the fused and the separate z form where both exist, unless
+ * DEMAG_TUNE_KEEP_FORM; then the x passes over the yg candidates; then the
+ * whole field sequence over the middle pass's kw x radix), keep the fastest
+ * and, when cache_path
  * is given, write it back
  * (temporary file + rename).  Measuring needs a bound plan (DEMAG_ESTATE) and,
  * for mesh parts, d_m and d_H laid out like the plan's vectors: d_m is only

@@ -772,7 +772,8 @@ int time_calls(hipStream_t s, F&& fn, double& us) {
 }
 
 // Measure the candidates of sub-plan sb and keep the fastest in its geometry.
-int tune_sub(demag_plan* p, Sub& sb, const float* d_m, float* d_H, hipStream_t s, TuneEntry& out) {
+int tune_sub(demag_plan* p, Sub& sb, const float* d_m, float* d_H, hipStream_t s, TuneEntry& out,
+             bool keep_form) {
   Geom& g = sb.g;
   // one field sequence without energy: forward x (and z) passes, middle
   // pass, inverse (z and) x passes
@@ -784,7 +785,7 @@ int tune_sub(demag_plan* p, Sub& sb, const float* d_m, float* d_H, hipStream_t s
     return run_inv(p, sb, inv_plain_args(p, sb, d_H, 0u, nullptr), s);
   };
   // fused x+z passes or separate z passes, where both exist
-  if (fused_ok(g) && zsep_ok(g)) {
+  if (!keep_form && fused_ok(g) && zsep_ok(g)) {
     const int z0 = g.zsep;
     double t[2] = {0.0, 0.0};
     for (int z = 0; z < 2; ++z) {
@@ -1330,7 +1331,9 @@ int demag_set_schedule(demag_plan* p, int part, int yg, int kw, int radix) {
 int demag_autotune(demag_plan* p, const float* d_m, float* d_H, const char* cache_path, unsigned flags,
                    int* measured, void* stream) {
   if (!p) return fail(DEMAG_EINVAL, "demag_autotune: plan is NULL");
-  if (flags & ~(unsigned)DEMAG_TUNE_FORCE) return fail(DEMAG_EINVAL, "demag_autotune: unknown flags");
+  if (flags & ~(unsigned)(DEMAG_TUNE_FORCE | DEMAG_TUNE_KEEP_FORM))
+    return fail(DEMAG_EINVAL, "demag_autotune: unknown flags");
+  const bool keep_form = (flags & DEMAG_TUNE_KEEP_FORM) != 0;
   if (measured) *measured = 0;
   TuneMap cache;
   std::string err;
@@ -1347,7 +1350,10 @@ int demag_autotune(demag_plan* p, const float* d_m, float* d_H, const char* cach
     const std::string key = part_key(p, i, devkey);
     const bool sub = i < (int)p->subs.size();
     auto it = cache.find(key);
-    if (it != cache.end() && !(flags & DEMAG_TUNE_FORCE)) {
+    // with the z form kept, an entry for the other form does not apply
+    const bool other_form = it != cache.end() && keep_form && sub && it->second.zsep >= 0 &&
+                            it->second.zsep != p->subs[i].g.zsep;
+    if (it != cache.end() && !(flags & DEMAG_TUNE_FORCE) && !other_form) {
       const TuneEntry& c = it->second;
       Geom& g = part_geom(p, i);
       const int z0 = g.zsep;
@@ -1369,7 +1375,8 @@ int demag_autotune(demag_plan* p, const float* d_m, float* d_H, const char* cach
     if (!p->has_work) return fail(DEMAG_ESTATE, "demag_autotune: plan was bound without a work buffer");
     if (sub && (!d_m || !d_H)) return fail(DEMAG_EINVAL, "demag_autotune: measuring needs m and H buffers");
     TuneEntry t;
-    const int rc = sub ? tune_sub(p, p->subs[i], d_m, d_H, s, t) : tune_group(p, p->groups[i - p->subs.size()], s, t);
+    const int rc = sub ? tune_sub(p, p->subs[i], d_m, d_H, s, t, keep_form)
+                       : tune_group(p, p->groups[i - p->subs.size()], s, t);
     if (rc != DEMAG_OK) return rc;
     cache[key] = t;
     ++nmeas;

@@ -48,16 +48,18 @@ class _Schedules:
     def set_z_passes(self, separate, part=0):
         _l.check(self._lib.demag_set_z_passes(self._p, int(part), int(bool(separate))))
 
-    def autotune(self, cache=None, force=False):
+    def autotune(self, cache=None, force=False, keep_form=False):
         """Pick each part's launch schedule by timing the candidates on the
         current stream (or from the JSON cache file `cache`, which is updated
-        with what was measured).  Returns the number of parts measured."""
+        with what was measured).  keep_form: keep the current z form (fused
+        or separate passes).  Returns the number of parts measured."""
         with torch.cuda.device(self.device):
             m = torch.zeros(self._vec_shape, dtype=torch.float32, device=self.device)
             H = torch.empty_like(m)
             n = ctypes.c_int()
             path = None if cache is None else str(cache).encode()
-            _l.check(self._lib.demag_autotune(self._p, _ptr(m), _ptr(H), path, _l.TUNE_FORCE if force else 0,
+            flags = (_l.TUNE_FORCE if force else 0) | (_l.TUNE_KEEP_FORM if keep_form else 0)
+            _l.check(self._lib.demag_autotune(self._p, _ptr(m), _ptr(H), path, flags,
                                               ctypes.byref(n), _stream()))
         return n.value
 

@@ -11,6 +11,7 @@ PBC_X, PBC_Y, PBC_Z = 1, 2, 4
 ACCUMULATE = 1
 NOALLOC_WORK_BYTES = 64 << 20
 TUNE_FORCE = 1
+TUNE_KEEP_FORM = 2
 
 _NAMES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOMEM: "ENOMEM", EHIP: "EHIP", ESTATE: "ESTATE"}
 

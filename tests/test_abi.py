@@ -262,7 +262,7 @@ def test_autotune_host_checks(lib, tmp_path):
     assert rc == L.OK
     n = ctypes.c_int(7)
     assert lib.demag_autotune(None, None, None, None, 0, ctypes.byref(n), None) == L.EINVAL
-    assert lib.demag_autotune(p, None, None, None, 2, ctypes.byref(n), None) == L.EINVAL
+    assert lib.demag_autotune(p, None, None, None, 4, ctypes.byref(n), None) == L.EINVAL
     for bad in ('{"entries": {}}', '{"format": "demag-schedule-cache/1", "entries": [1]}', "{", "[]",
                 '{"format": "demag-schedule-cache/1", "entries": {"k": {"kw": }}}',
                 '{"format": "demag-schedule-cache/1"} trailing'):

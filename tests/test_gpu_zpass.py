@@ -136,6 +136,12 @@ def test_tuner_chooses_between_the_forms(torch, tmp_path):
     _check(torch, plan, n, h, 155)
     text = (tmp_path / "sched.json").read_text()
     assert '"zsep": ' in text
+    # a forced form survives tuning with keep_form
+    other = not plan.z_passes()
+    plan.set_z_passes(other)
+    plan.autotune(cache=tmp_path / "sched.json", keep_form=True)
+    assert plan.z_passes() == other
+    _check(torch, plan, n, h, 156)
 
 
 def test_full_size_1024x1024x32(torch):
