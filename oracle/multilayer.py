@@ -150,12 +150,15 @@ def field_at(meshes, Ms, targets):
     return out
 
 
-def field(meshes, Ms):
+def field(meshes, Ms, only=None):
     """H of every cell of every mesh by the direct sum (small meshes only):
     all target cells of mesh p against all source cells of mesh q at once.
-    Returns a list of arrays (3, nz, ny, nx)."""
+    only: indices of the target meshes to evaluate (default: all).
+    Returns a list of arrays (3, nz, ny, nx), one per evaluated mesh."""
     res = []
     for p, (n_p, h_p, o_p) in enumerate(meshes):
+        if only is not None and p not in only:
+            continue
         Zt, Yt, Xt = (a.ravel() for a in centres(n_p, h_p, o_p))
         H = np.zeros((3, Xt.size))
         for (n_q, h_q, o_q), M in zip(meshes, Ms):
@@ -163,6 +166,65 @@ def field(meshes, Ms):
             M = np.asarray(M, np.float64).reshape(3, -1)
             N = tensor_unequal(Xt[:, None] - Xs[None, :], Yt[:, None] - Ys[None, :], Zt[:, None] - Zs[None, :],
                                h_p, h_q)
+            xx, yy, zz, xy, xz, yz = N
+            H[0] -= xx @ M[0] + xy @ M[1] + xz @ M[2]
+            H[1] -= xy @ M[0] + yy @ M[1] + yz @ M[2]
+            H[2] -= xz @ M[0] + yz @ M[1] + zz @ M[2]
+        nx, ny, nz = n_p
+        res.append(H.reshape(3, nz, ny, nx))
+    return res
+
+
+def periods(meshes, pbc):
+    """Period of a coupled collection along each periodic axis (Sec. 3,
+    multiple images): the collection repeats as a whole, so every mesh must
+    start at the same coordinate and span the same length along that axis;
+    the period is that length.  pbc = (bool, bool, bool).  Returns (Px, Py, Pz),
+    0 along open axes."""
+    out = []
+    for a in range(3):
+        if not pbc[a]:
+            out.append(0.0)
+            continue
+        spans = {round(n[a] * h[a] / 1e-15) for n, h, _ in meshes}
+        starts = {round(o[a] / 1e-15) for _, _, o in meshes}
+        if len(spans) != 1 or len(starts) != 1:
+            raise ValueError("periodic axis: every mesh must share its start and its span")
+        n, h, _ = meshes[0]
+        out.append(n[a] * h[a])
+    return tuple(out)
+
+
+def image_shifts(meshes, pbc, images):
+    """Shift vectors k o P of the symmetric image set, |k_a| <= images on the
+    periodic axes."""
+    P = periods(meshes, pbc)
+    rng = [range(-images, images + 1) if pbc[a] else range(0, 1) for a in range(3)]
+    return [(i * P[0], j * P[1], k * P[2]) for i in rng[0] for j in rng[1] for k in rng[2]]
+
+
+def field_periodic(meshes, Ms, pbc, images):
+    """Eq. 4 over a coupled collection with periodic axes by multiple images:
+    the field of the collection repeated `images` times on either side of
+    each periodic axis, read in its central copy,
+    H_t = -sum_q sum_j sum_k N(r_t - r_j - k o P, h_p, h_q) M_j.
+    Direct sum (small meshes).  Returns a list of arrays (3, nz, ny, nx)."""
+    shifts = np.asarray(image_shifts(meshes, pbc, images))
+    res = []
+    for p, (n_p, h_p, o_p) in enumerate(meshes):
+        Zt, Yt, Xt = (a.ravel() for a in centres(n_p, h_p, o_p))
+        H = np.zeros((3, Xt.size))
+        for (n_q, h_q, o_q), M in zip(meshes, Ms):
+            Zs, Ys, Xs = (a.ravel() for a in centres(n_q, h_q, o_q))
+            M = np.asarray(M, np.float64).reshape(3, -1)
+            dX, dY, dZ = Xt[:, None] - Xs[None, :], Yt[:, None] - Ys[None, :], Zt[:, None] - Zs[None, :]
+            # all images of every pair at once, in groups of about 2^20 offsets
+            N = np.zeros((6,) + dX.shape)
+            per = max(1, (1 << 20) // dX.size)
+            for g0 in range(0, len(shifts), per):
+                sh = shifts[g0:g0 + per]
+                N += tensor_unequal(dX[None] - sh[:, 0, None, None], dY[None] - sh[:, 1, None, None],
+                                    dZ[None] - sh[:, 2, None, None], h_p, h_q).sum(axis=1)
             xx, yy, zz, xy, xz, yz = N
             H[0] -= xx @ M[0] + xy @ M[1] + xz @ M[2]
             H[1] -= xy @ M[0] + yy @ M[1] + yz @ M[2]

@@ -126,3 +126,62 @@ def test_gradient_matches_central_differences():
             Mm[q][idx] -= 1.0
             fd = (L(Mp) - L(Mm)) / 2.0
             assert abs(fd - grad[q][idx]) <= 1e-9 * max(1.0, abs(fd))
+
+
+# --- periodic in-plane axes (Sec. 3, multiple images, on a coupled stack) ---
+
+STACK = [((4, 2, 2), (1e-9, 1e-9, 1e-9), (0.0, 0.0, 0.0)),
+         ((4, 2, 1), (1e-9, 1e-9, 1e-9), (0.0, 0.0, 3e-9)),
+         ((2, 1, 1), (2e-9, 2e-9, 2e-9), (0.0, 0.0, 5e-9))]
+
+
+def test_periodic_collection_equals_the_repeated_collection():
+    # the image-summed field is the open-boundary field of the collection
+    # repeated (2K+1)^2 times in the plane, read in its central copy
+    K, pbc = 1, (True, True, False)
+    Ms = [8e5 * inputs.unit_sphere(n, seed=40 + i).astype(np.float64) for i, (n, _, _) in enumerate(STACK)]
+    got = ml.field_periodic(STACK, Ms, pbc, K)
+    P = ml.periods(STACK, pbc)
+    assert P == pytest.approx((4e-9, 2e-9, 0.0), rel=1e-12)
+    tiled, tiled_M = [], []
+    for i in range(-K, K + 1):
+        for j in range(-K, K + 1):
+            for (n, h, o), M in zip(STACK, Ms):
+                tiled.append((n, h, (o[0] + i * P[0], o[1] + j * P[1], o[2])))
+                tiled_M.append(M)
+    central = 3 * ((2 * K + 1) * K + K)              # index of the (0, 0) copy of the first mesh
+    want = ml.field(tiled, tiled_M, only=[central, central + 1, central + 2])
+    for g, w in zip(got, want):
+        assert np.max(np.abs(g - w)) <= 1e-12 * np.max(np.abs(w))
+
+
+def test_periodic_axes_need_a_common_span():
+    with pytest.raises(ValueError):
+        ml.periods([((4, 4, 1), (1e-9, 1e-9, 1e-9), (0, 0, 0)), ((3, 4, 1), (1e-9, 1e-9, 1e-9), (0, 0, 2e-9))],
+                   (True, False, False))
+
+
+@pytest.mark.parametrize("axis", [2, 0])
+def test_periodic_stack_tends_to_the_infinite_slab(axis):
+    # a stack of layers periodic in x and y and uniformly magnetized is, as
+    # K grows, a set of infinite slabs: perpendicular M gives H = -M inside
+    # every layer, in-plane M gives H = 0 (coarse layer with 2x in-plane cells)
+    stack = [((2, 2, 2), (5e-9, 5e-9, 1e-9), (0.0, 0.0, 0.0)),
+             ((2, 2, 1), (5e-9, 5e-9, 1e-9), (0.0, 0.0, 3e-9)),
+             ((1, 1, 2), (10e-9, 10e-9, 2e-9), (0.0, 0.0, 6e-9))]
+    Ms = 1e6
+    errs = []
+    for K in (3, 12):
+        Mlist = []
+        for n, _, _ in stack:
+            M = np.zeros((3, n[2], n[1], n[0]))
+            M[axis] = Ms
+            Mlist.append(M)
+        H = ml.field_periodic(stack, Mlist, (True, True, False), K)
+        want = np.zeros(3)
+        want[axis] = -Ms if axis == 2 else 0.0
+        err = max(np.max(np.abs(Hp - want[:, None, None, None])) for Hp in H) / Ms
+        # a finite film of side L = (2K+1) P deviates by O(thickness / L)
+        assert err < 4 * 4e-9 / ((2 * K + 1) * 10e-9), (K, err)
+        errs.append(err)
+    assert errs[1] < 0.5 * errs[0]
