@@ -50,7 +50,7 @@ typedef struct demag_plan demag_plan;
 enum {
   DEMAG_OK = 0,
   DEMAG_EINVAL = -1,        /* invalid argument (null pointer, bad size, NaN cell) */
-  DEMAG_EUNSUPPORTED = -2,  /* valid but not supported (size limits, periodic coupled groups) */
+  DEMAG_EUNSUPPORTED = -2,  /* valid but not supported (size limits, group shapes) */
   DEMAG_ENOMEM = -3,        /* host or set-up device allocation failed */
   DEMAG_EHIP = -4,          /* a HIP runtime call failed */
   DEMAG_ESTATE = -5         /* wrong call order (field before bind, bind twice) */
@@ -157,9 +157,12 @@ int demag_backward(const demag_plan* plan, const float* d_G, const float* d_Ms, 
  * identical geometry share one kernel spectrum and one launch per pass.
  * Vectors of all meshes are concatenated in mesh order, each mesh SoA
  * [3][nz][ny][nx], at the float offsets given by demag_batch_layout.
- * pbc_flags / pbc_images apply to every independent mesh as in demag_setup;
- * with periodic axes, coupled groups return DEMAG_EUNSUPPORTED.  Host only,
- * like demag_setup. */
+ * pbc_flags / pbc_images apply to every independent mesh as in demag_setup
+ * and to every coupled group along x and y (Sec. 3, multiple images: the
+ * group repeats as a whole, with the pair tensors summed over the images;
+ * every mesh of the group must span the whole group along a periodic axis,
+ * else DEMAG_EUNSUPPORTED).  A coupled group with periodic z returns
+ * DEMAG_EUNSUPPORTED.  Host only, like demag_setup. */
 int demag_setup_batch(demag_plan** out, int nmesh, const int* dims, const double* cells, const double* origins,
                       const int* groups, unsigned pbc_flags, int pbc_images);
 

@@ -48,6 +48,8 @@ struct Group {
   std::vector<double> pdx, pdy, pz;
   Geom g{};                        // fine lattice: nx = Lx, ny = Ly, nz = Nz = P
   double fx = 0, fy = 0;
+  unsigned pbc = 0;                // periodic in-plane axes (bit 0 x, bit 1 y)
+  int images = 0;
   size_t k_off = 0, pl_off = 0, t_off = 0, s_off = 0, e_off = 0;
   float2* K = nullptr;
   PlaneInfo* pl = nullptr;
@@ -263,7 +265,7 @@ void layout(demag_plan* p) {
 
 // Coupled group from meshes idx (validated; host only).
 int make_group(const std::vector<int>& idx, const int* dims, const double* cells, const double* origins,
-               const std::vector<long long>& offsets, Group& G) {
+               const std::vector<long long>& offsets, unsigned pbc, int images, Group& G) {
   const char* who = "demag_setup_batch";
   double fx = 1e300, fy = 1e300, X0 = 1e300, Y0 = 1e300;
   for (int i : idx) {
@@ -314,6 +316,23 @@ int make_group(const std::vector<int>& idx, const int* dims, const double* cells
   }
   const int P = (int)G.planes.size();
   if (P > MAXP) return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": a coupled group has at most 8 z planes");
+  // periodic in-plane axes: the group repeats as a whole, so every mesh spans
+  // the whole lattice along such an axis
+  for (int i : idx) {
+    const int n[2] = {dims[3 * i], dims[3 * i + 1]};
+    int s[2], o[2];
+    pow2ratio(cells[3 * i], fx, s[0]);
+    pow2ratio(cells[3 * i + 1], fy, s[1]);
+    lattice(origins[3 * i] - X0, fx, o[0]);
+    lattice(origins[3 * i + 1] - Y0, fy, o[1]);
+    const int L[2] = {Lx, Ly};
+    for (int a = 0; a < 2; ++a)
+      if (((pbc >> a) & 1u) && (o[a] != 0 || n[a] * s[a] != L[a]))
+        return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": along a periodic axis every mesh of a coupled group "
+                                                          "must span the whole group");
+  }
+  G.pbc = pbc & 3u;
+  G.images = G.pbc ? images : 0;
   if (Lx < 2 || Lx > 2048 || Ly > 1024)
     return fail(DEMAG_EUNSUPPORTED, std::string(who) + ": coupled lattice must span 2..2048 x 1..1024 fine cells");
   Geom& g = G.g;
@@ -385,6 +404,10 @@ int build_group(const Group& G, hipStream_t s) {
         pg.oy = G.pdy[p] - G.pdy[q];
         pg.oz = G.pz[p] - G.pz[q];
         pg.Nx = g.Nx; pg.Ny = g.Ny; pg.Lx = g.nx; pg.Ly = g.ny;
+        pg.kx = (G.pbc & 1u) ? G.images : 0;
+        pg.ky = (G.pbc & 2u) ? G.images : 0;
+        pg.px = g.nx * G.fx;
+        pg.py = g.ny * G.fy;
         if ((e = launch_pair_tensor(buf, pg, gl, s)) != hipSuccess) { rc = fail_hip(e, "pair tensor"); break; }
         if ((e = launch_fft64(buf, g.lnx, 1, g.Nx, g.Ny, (long long)cnt, 6 * g.Ny, d_tw, s)) != hipSuccess) {
           rc = fail_hip(e, "pair x transform"); break;
@@ -978,10 +1001,10 @@ int demag_setup_batch(demag_plan** out, int nmesh, const int* dims, const double
   if (pbc_flags & ~7u) return fail(DEMAG_EINVAL, "demag_setup_batch: unknown boundary flags");
   if (pbc_flags && pbc_images > MAX_IMAGES)
     return fail(DEMAG_EINVAL, "demag_setup_batch: at most 1000 images per side");
-  if (pbc_flags && groups)
+  if ((pbc_flags & DEMAG_PBC_Z) && groups)
     for (int i = 0; i < nmesh; ++i)
       if (groups[i] >= 0)
-        return fail(DEMAG_EUNSUPPORTED, "demag_setup_batch: periodic boundaries are not supported for coupled groups");
+        return fail(DEMAG_EUNSUPPORTED, "demag_setup_batch: coupled groups take periodic x and y only");
   demag_plan* p = new (std::nothrow) demag_plan;
   if (!p) return fail(DEMAG_ENOMEM, "demag_setup_batch: out of host memory");
   p->batch = true;
@@ -1010,7 +1033,8 @@ int demag_setup_batch(demag_plan** out, int nmesh, const int* dims, const double
       for (int i = 0; i < nmesh; ++i)
         if (groups[i] == id) idx.push_back(i);
       Group G;
-      const int rc = make_group(idx, dims, cells, origins, p->offsets, G);
+      const int rc = make_group(idx, dims, cells, origins, p->offsets, pbc_flags,
+                                pbc_flags ? (pbc_images > 0 ? pbc_images : DEFAULT_IMAGES) : 0, G);
       if (rc != DEMAG_OK) {
         delete p;
         return rc;

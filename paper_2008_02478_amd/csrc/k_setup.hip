@@ -439,7 +439,9 @@ __device__ void tensor_unequal_dev(double X, double Y, double Z, const double* h
 
 // One plane pair on the padded fine grid [6][Ny][Nx] (FP64 complex, imaginary
 // part 0): lattice offset u = i for i < Lx, i - Nx for i > Nx - Lx, none
-// (zero) in between; the same along y.
+// (zero) in between; the same along y.  Along periodic in-plane axes the
+// tensor is summed over the images, offsets shifted by whole periods (Sec. 3,
+// multiple images).
 __global__ void k_pair_tensor(double2* __restrict__ out, PairGeom pg, GLTable gl) {
   const size_t cnt = (size_t)pg.Nx * pg.Ny;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -448,8 +450,15 @@ __global__ void k_pair_tensor(double2* __restrict__ out, PairGeom pg, GLTable gl
   const int u = i < pg.Lx ? i : (i > pg.Nx - pg.Lx ? i - pg.Nx : INT_MIN);
   const int v = j < pg.Ly ? j : (j > pg.Ny - pg.Ly ? j - pg.Ny : INT_MIN);
   double N[6] = {0, 0, 0, 0, 0, 0};
-  if (u != INT_MIN && v != INT_MIN)
-    tensor_unequal_dev(u * pg.fx + pg.ox, v * pg.fy + pg.oy, pg.oz, pg.ht, pg.hs, gl, N);
+  if (u != INT_MIN && v != INT_MIN) {
+    // summed over the images of periodic in-plane axes (kx = ky = 0: open)
+    for (int a = -pg.kx; a <= pg.kx; ++a)
+      for (int b = -pg.ky; b <= pg.ky; ++b) {
+        double Ni[6];
+        tensor_unequal_dev(u * pg.fx + pg.ox + a * pg.px, v * pg.fy + pg.oy + b * pg.py, pg.oz, pg.ht, pg.hs, gl, Ni);
+        for (int q = 0; q < 6; ++q) N[q] += Ni[q];
+      }
+  }
   for (int q = 0; q < 6; ++q) out[q * cnt + idx] = make_double2(N[q], 0.0);
 }
 

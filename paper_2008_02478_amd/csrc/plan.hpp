@@ -112,6 +112,10 @@ struct PairGeom {
   double ht[3], hs[3];
   double fx, fy, ox, oy, oz;
   int Nx, Ny, Lx, Ly;
+  // periodic in-plane axes (multiple images): images on either side along x
+  // and y (0: open axis) and the periods (the lattice spans) in metres
+  int kx, ky;
+  double px, py;
 };
 
 // Coupled layers (Sec. 3, Eq. 4): every z plane of every mesh of a group is

@@ -289,8 +289,21 @@ def test_periodic_batch_rules(lib):
     orig = (ctypes.c_double * (3 * k))(0.0, 0.0, 0.0, 0.0, 0.0, 3e-9, 0.0, 0.0, 0.0)
     p = ctypes.c_void_p()
     grp = (ctypes.c_int * k)(0, 0, -1)
-    assert lib.demag_setup_batch(ctypes.byref(p), k, dims, cells, orig, grp, L.PBC_X, 4) == L.EUNSUPPORTED
+    # coupled groups: periodic x and y, not z
+    assert lib.demag_setup_batch(ctypes.byref(p), k, dims, cells, orig, grp, L.PBC_X, 4) == L.OK
+    lib.demag_destroy(p)
+    assert lib.demag_setup_batch(ctypes.byref(p), k, dims, cells, orig, grp, L.PBC_X | L.PBC_Y, 0) == L.OK
+    lib.demag_destroy(p)
+    assert lib.demag_setup_batch(ctypes.byref(p), k, dims, cells, orig, grp, L.PBC_Z, 4) == L.EUNSUPPORTED
     assert not p.value
+    # along a periodic axis every mesh of the group spans the whole group
+    dims2 = (ctypes.c_int * (3 * k))(16, 16, 1, 12, 16, 1, 8, 8, 2)
+    assert lib.demag_setup_batch(ctypes.byref(p), k, dims2, cells, orig, grp, L.PBC_X, 4) == L.EUNSUPPORTED
+    assert lib.demag_setup_batch(ctypes.byref(p), k, dims2, cells, orig, grp, L.PBC_Y, 4) == L.OK
+    lib.demag_destroy(p)
+    orig2 = (ctypes.c_double * (3 * k))(0.0, 0.0, 0.0, 0.0, 2e-9, 3e-9, 0.0, 0.0, 0.0)
+    dims3 = (ctypes.c_int * (3 * k))(16, 18, 1, 16, 16, 1, 8, 8, 2)
+    assert lib.demag_setup_batch(ctypes.byref(p), k, dims3, cells, orig2, grp, L.PBC_Y, 4) == L.EUNSUPPORTED
     grp = (ctypes.c_int * k)(-1, -1, -1)
     assert lib.demag_setup_batch(ctypes.byref(p), k, dims, cells, orig, grp, L.PBC_X | L.PBC_Y, 4) == L.OK
     lib.demag_destroy(p)
