@@ -240,7 +240,8 @@ k_mid(MidArgs a) {
   // y (an odd pitch, so the lanes of a job, which read consecutive y, hit
   // distinct LDS banks)
   constexpr int KWP = KW + 1;
-  float2* stage = smem;                     // 3 components x ny * KWP points
+  constexpr int CST = M * KWP;              // component stride of the staging: M rows (zeros past ny)
+  float2* stage = smem;                     // 3 components x M * KWP points
   float2* scr = smem + (size_t)job * lds_points<M, R>();   // per-job scratch (aliases stage)
   const size_t cstride = (size_t)a.Nz * a.nTiles * ny * TILE;
   float2* blk0 = a.T + ((size_t)kz * a.nTiles + tile) * ny * TILE + half * KW;
@@ -308,27 +309,28 @@ k_mid(MidArgs a) {
       if (NY >= 4 && tid < NKC * KW && kx0 + tid / NKC < a.Kx)
         knv = a.K[(size_t)NKC * a.Kzh * a.Kx * KYP + ((size_t)kzf * a.Kx + kx0) * NKC + tid];
     }
+    // all M rows staged (rows past ny were loaded as zeros), so the reads
+    // below need no bounds and their offsets are compile-time constants
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
 #pragma unroll
       for (int i = 0; i < ITER; ++i) {
         const int e = tid + i * NTH;
-        if (e < nv) {
+        if ((NYMAX * V) % NTH == 0 || e < NYMAX * V) {
           const int y = e / V, q = e - y * V;
-          float2* const d = stage + c * ny * KWP + y * KWP + 2 * q;
+          float2* const d = stage + c * CST + y * KWP + 2 * q;
           d[0] = make_float2(pre[c][i].x, pre[c][i].y);
           d[1] = make_float2(pre[c][i].z, pre[c][i].w);
         }
       }
     }
     __syncthreads();
+    {
+      const float2* const src = stage + t * KWP + w;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int j = 0; j < R; ++j) {
-        const int y = t + T * j;
-        v[c][j] = (valid && y < ny) ? stage[c * ny * KWP + y * KWP + w] : make_float2(0.f, 0.f);
-      }
+        for (int j = 0; j < R; ++j) v[c][j] = src[c * CST + T * j * KWP];
     }
     if constexpr (NRES == 2) {
       if (r) {
@@ -463,14 +465,12 @@ k_mid(MidArgs a) {
 
   // sum the two residues of the three components in LDS and store
   __syncthreads();
+  float2* const dstg = stage + t * KWP + w;   // row y = t + T j of this lane's line
   if (lane_act && r == NRES - 1) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int j = 0; j < R; ++j) {
-        const int y = t + T * j;
-        if (y < ny) stage[c * ny * KWP + y * KWP + w] = v[c][j];
-      }
+      for (int j = 0; j < R; ++j) dstg[c * CST + T * j * KWP] = v[c][j];
   }
   __syncthreads();
   if constexpr (NRES == 2) {
@@ -478,10 +478,7 @@ k_mid(MidArgs a) {
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-          const int y = t + T * j;
-          if (y < ny) stage[c * ny * KWP + y * KWP + w] = cadd(stage[c * ny * KWP + y * KWP + w], v[c][j]);
-        }
+        for (int j = 0; j < R; ++j) dstg[c * CST + T * j * KWP] = cadd(dstg[c * CST + T * j * KWP], v[c][j]);
     }
     __syncthreads();
   }
@@ -492,7 +489,7 @@ k_mid(MidArgs a) {
       float4* b4 = reinterpret_cast<float4*>(blk0 + c * cstride);
       for (int q = tid; q < ny * V; q += blockDim.x) {
         const int y = q / V, s2 = q - y * V;
-        const float2* const src = stage + c * ny * KWP + y * KWP + 2 * s2;
+        const float2* const src = stage + c * CST + y * KWP + 2 * s2;
         const float2 lo = src[0], hi = src[1];
         b4[(unsigned)y * (TILE / 2) + s2] = make_float4(lo.x, lo.y, hi.x, hi.y);
       }
@@ -760,7 +757,7 @@ static hipError_t mid_launch(const Geom& g, const MidArgs& a, hipStream_t s) {
   constexpr int M = NY > 1 ? NY / 2 : 1;
   constexpr int NRES = NY > 1 ? 2 : 1;
   size_t lds = (size_t)NRES * KW * lds_points<M, R>() * sizeof(float2);
-  const size_t st = (size_t)3 * g.ny * (KW + 1) * sizeof(float2);   // staging of the three components
+  const size_t st = (size_t)3 * M * (KW + 1) * sizeof(float2);   // staging of the three components
   if (st > lds) lds = st;
   const size_t klp = NRES == 2 ? kernel_row_pitch(NY) + 4 : kernel_row_pitch(NY);
   const size_t kr = (MODE == 0 || MODE == 3) ? (size_t)KW * (MODE == 3 ? 3 : 6) * klp * sizeof(float) : 0;
