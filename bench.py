@@ -320,6 +320,8 @@ def main():
     ap.add_argument("--schedule-cache", default=None, help="JSON schedule cache to apply (and extend)")
     ap.add_argument("--z-form", choices=("auto", "fused", "separate"), default="auto",
                     help="z transform inside the x passes (fused) or in separate passes; auto: the tuner's choice")
+    ap.add_argument("--schedule", default=None, metavar="YG,KW,RADIX",
+                    help="launch schedule of the mesh after tuning (0 keeps a field)")
     ap.add_argument("--main-only", action="store_true",
                     help="time the field + backward step only (no batch, RK4 or Oersted legs), e.g. under a profiler")
     args = ap.parse_args()
@@ -354,6 +356,9 @@ def main():
     if not args.no_tune:
         plan.autotune(cache=args.schedule_cache, keep_form=args.z_form != "auto")
     tune_s = time.time() - t0
+    if args.schedule:
+        yg, kw, radix = (int(v) for v in args.schedule.split(","))
+        plan.set_schedule(0, yg, kw, radix)
     m = torch.from_numpy(m_np).to(dev)
     G = torch.from_numpy(G_np).to(dev)
     H = torch.empty_like(m)
