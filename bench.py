@@ -322,6 +322,8 @@ def main():
                     help="z transform inside the x passes (fused) or in separate passes; auto: the tuner's choice")
     ap.add_argument("--schedule", default=None, metavar="YG,KW,RADIX",
                     help="launch schedule of the mesh after tuning (0 keeps a field)")
+    ap.add_argument("--legs", default="batch,llg,oersted",
+                    help="comma-separated secondary legs to run after the main step (batch, llg, oersted)")
     ap.add_argument("--main-only", action="store_true",
                     help="time the field + backward step only (no batch, RK4 or Oersted legs), e.g. under a profiler")
     args = ap.parse_args()
@@ -495,9 +497,14 @@ def main():
         "copy_gbs": copy_gbs, "frac_of_copy": step_gbs / copy_gbs, "torch_copy_gbs": torch_copy_gbs,
         "compulsory_gbs": 2 * comp / (ms_step * 1e-3) / 1e9,
         "note": "two field evaluations (forward with energy, backward) per step; whole-step time"}
-    if not args.main_only:
+    legs = set() if args.main_only else {x for x in args.legs.split(",") if x}
+    if legs - {"batch", "llg", "oersted"}:
+        ap.error(f"unknown legs {sorted(legs - {'batch', 'llg', 'oersted'})}")
+    if "batch" in legs:
         out["batched_multi_mesh"] = bench_batch(torch, tune=not args.no_tune, cache=args.schedule_cache)
+    if "llg" in legs:
         out["llg_rk4"] = bench_llg(torch, plan, m_np)
+    if "oersted" in legs:
         out["oersted"] = bench_oersted(torch, n, h, wl["seed"] + 200, tune=not args.no_tune,
                                        cache=args.schedule_cache)
 

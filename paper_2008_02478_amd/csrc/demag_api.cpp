@@ -51,12 +51,30 @@ struct Group {
   unsigned pbc = 0;                // periodic in-plane axes (bit 0 x, bit 1 y)
   int images = 0;
   size_t k_off = 0, pl_off = 0, t_off = 0, s_off = 0, e_off = 0;
-  float2* K = nullptr;
+  float* K = nullptr;               // pair spectra (complex, or one float per frequency for parity pairs)
   PlaneInfo* pl = nullptr;
   float2* T = nullptr;
   float2* S = nullptr;
   double* epart = nullptr;
   int npairs() const { const int P = (int)planes.size(); return P * (P + 1) / 2; }
+  // pairs (p <= q, in order) whose planes share the in-plane cell centres:
+  // their spectra are stored as one float per frequency and component
+  unsigned long long parity_pairs() const {
+    unsigned long long m = 0;
+    const int P = (int)planes.size();
+    int i = 0;
+    for (int p = 0; p < P; ++p)
+      for (int q = p; q < P; ++q, ++i)
+        if (pdx[p] == pdx[q] && pdy[p] == pdy[q]) m |= 1ull << i;
+    return m;
+  }
+  // floats of all pair spectra (6 components per frequency each)
+  size_t pair_floats(size_t npt) const {
+    const unsigned long long m = parity_pairs();
+    size_t n = 0;
+    for (int i = 0; i < npairs(); ++i) n += ((m >> i) & 1ull) ? 6 * npt : 12 * npt;
+    return n;
+  }
 };
 
 }  // namespace
@@ -249,7 +267,7 @@ void layout(demag_plan* p) {
     const int P = (int)G.planes.size();
     const size_t npt = (size_t)g.Kx * g.Ny;
     G.k_off = kb;
-    kb += align256((size_t)G.npairs() * 6 * npt * sizeof(float2));
+    kb += align256(G.pair_floats(npt) * sizeof(float));
     G.pl_off = kb;
     kb += align256((size_t)P * sizeof(PlaneInfo));
     G.t_off = wb;
@@ -392,6 +410,7 @@ int build_group(const Group& G, hipStream_t s) {
       rc = fail_hip(e, "twiddle upload"); break;
     }
     int pair = 0;
+    size_t koff = 0;   // float offset of the pair's spectrum
     for (int p = 0; p < P && rc == DEMAG_OK; ++p) {
       for (int q = p; q < P; ++q, ++pair) {
         PairGeom pg{};
@@ -415,8 +434,10 @@ int build_group(const Group& G, hipStream_t s) {
         if (g.Ny > 1 && (e = launch_fft64(buf, g.lny, g.Nx, 1, g.Nx, (long long)cnt, 6 * g.Nx, d_tw, s)) != hipSuccess) {
           rc = fail_hip(e, "pair y transform"); break;
         }
-        float2* dst = G.K + (size_t)pair * 6 * g.Kx * g.Ny;
-        if ((e = launch_pair_pack(buf, dst, g.Nx, g.Ny, g.Kx, -1.0 / ((double)g.Nx * g.Ny), s)) != hipSuccess) {
+        const int parity = (int)((G.parity_pairs() >> pair) & 1ull);
+        float* dst = G.K + koff;
+        koff += (parity ? 6 : 12) * (size_t)g.Kx * g.Ny;
+        if ((e = launch_pair_pack(buf, dst, g.Nx, g.Ny, g.Kx, -1.0 / ((double)g.Nx * g.Ny), parity, s)) != hipSuccess) {
           rc = fail_hip(e, "pair pack"); break;
         }
       }
@@ -445,7 +466,7 @@ int run_groups(const demag_plan* p, const float* d_in, const float* ms_mesh, flo
     if (e != hipSuccess) return fail_hip(e, "layer forward pass");
     const MidArgs ma = group_mid_args(p, G);
     if ((e = launch_mid_split(g, ma, 1, s)) != hipSuccess) return fail_hip(e, "layer y pass");
-    CoupleArgs ca{G.S, G.K, G.pl, g.Kx, g.Ny, g.Nx, (d_energy && !backward) ? G.epart : nullptr};
+    CoupleArgs ca{G.S, G.K, G.pl, g.Kx, g.Ny, g.Nx, (d_energy && !backward) ? G.epart : nullptr, G.parity_pairs()};
     if ((e = launch_couple(P, ca, s)) != hipSuccess) return fail_hip(e, "layer coupling");
     if ((e = launch_mid_split(g, ma, 2, s)) != hipSuccess) return fail_hip(e, "layer inverse y pass");
     if ((e = launch_layer_x(g.lnx, la, true, s)) != hipSuccess) return fail_hip(e, "layer inverse pass");
@@ -1141,7 +1162,7 @@ int demag_bind(demag_plan* p, void* d_kernel, void* d_work, void* stream) {
   }
   p->tw = reinterpret_cast<float2*>(kb);
   for (Group& G : p->groups) {
-    G.K = reinterpret_cast<float2*>(kb + G.k_off);
+    G.K = reinterpret_cast<float*>(kb + G.k_off);
     G.pl = reinterpret_cast<PlaneInfo*>(kb + G.pl_off);
     G.T = reinterpret_cast<float2*>(wb + G.t_off);
     G.S = reinterpret_cast<float2*>(wb + G.s_off);

@@ -120,13 +120,27 @@ __global__ void __launch_bounds__(256) k_couple(CoupleArgs a) {
     }
   }
   int pair = 0;
+  size_t koff = 0;   // float offset of the pair's spectrum
 #pragma unroll
   for (int p = 0; p < P; ++p) {
 #pragma unroll
     for (int q = p; q < P; ++q) {
       float2 k6[6];
+      if ((a.parity_pairs >> pair) & 1ull) {
+        // real xx yy zz xy, imaginary xz yz: one float each
+        const float* const kr = a.K + koff;
 #pragma unroll
-      for (int e = 0; e < 6; ++e) k6[e] = act ? a.K[((size_t)pair * 6 + e) * npt + pt] : make_float2(0.f, 0.f);
+        for (int e = 0; e < 6; ++e) {
+          const float v = act ? kr[(size_t)e * npt + pt] : 0.f;
+          k6[e] = e < 4 ? make_float2(v, 0.f) : make_float2(0.f, v);
+        }
+        koff += (size_t)6 * npt;
+      } else {
+        const float2* const kc = reinterpret_cast<const float2*>(a.K + koff);
+#pragma unroll
+        for (int e = 0; e < 6; ++e) k6[e] = act ? kc[(size_t)e * npt + pt] : make_float2(0.f, 0.f);
+        koff += (size_t)12 * npt;
+      }
       sym_mac(H[p], k6, M[q], 1.f, false);
       if (q != p) sym_mac(H[q], k6, M[p], vol[p] / vol[q], true);
       ++pair;

@@ -491,10 +491,13 @@ __global__ void k_fft64_lines(double2* __restrict__ data, int logN, long long es
   for (int i = threadIdx.x; i < N; i += blockDim.x) base[(long long)i * es] = buf[i];
 }
 
-// [6][Ny][Nx] FP64 spectrum -> one pair's block K[6][Kx][NY] (FP32 complex)
-// times scale, ky stored by residue (r * NY/2 + k' for ky = 2k' + r).
-__global__ void k_pair_pack(const double2* __restrict__ in, float2* __restrict__ K, int Nx, int Ny, int Kx,
-                            double scale) {
+// [6][Ny][Nx] FP64 spectrum -> one pair's block K[6][Kx][NY] times scale, ky
+// stored by residue (r * NY/2 + k' for ky = 2k' + r).  FP32 complex, or for a
+// pair without in-plane centre offset (parity != 0) one FP32 per frequency:
+// the real part of xx yy zz xy, the imaginary part of xz yz (the other part
+// is zero by the parity of the tensor in the in-plane offsets).
+__global__ void k_pair_pack(const double2* __restrict__ in, float* __restrict__ K, int Nx, int Ny, int Kx,
+                            double scale, int parity) {
   const size_t tot = (size_t)6 * Kx * Ny;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= tot) return;
@@ -504,7 +507,11 @@ __global__ void k_pair_pack(const double2* __restrict__ in, float2* __restrict__
   const int M = Ny > 1 ? Ny / 2 : 1;
   const int ky = Ny > 1 ? 2 * (ry % M) + ry / M : 0;
   const double2 v = in[(size_t)c * Nx * Ny + (size_t)ky * Nx + kx];
-  K[idx] = make_float2((float)(scale * v.x), (float)(scale * v.y));
+  if (parity) {
+    K[idx] = (float)(scale * (c < 4 ? v.x : v.y));
+  } else {
+    reinterpret_cast<float2*>(K)[idx] = make_float2((float)(scale * v.x), (float)(scale * v.y));
+  }
 }
 
 }  // namespace demag
@@ -576,9 +583,11 @@ hipError_t launch_fft64(double2* data, int logN, long long es, long long ls, int
   return hipGetLastError();
 }
 
-hipError_t launch_pair_pack(const double2* in, float2* K, int Nx, int Ny, int Kx, double scale, hipStream_t s) {
+hipError_t launch_pair_pack(const double2* in, float* K, int Nx, int Ny, int Kx, double scale, int parity,
+                            hipStream_t s) {
   const size_t tot = (size_t)6 * Kx * Ny;
-  hipLaunchKernelGGL(k_pair_pack, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, in, K, Nx, Ny, Kx, scale);
+  hipLaunchKernelGGL(k_pair_pack, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, in, K, Nx, Ny, Kx, scale,
+                     parity);
   return hipGetLastError();
 }
 

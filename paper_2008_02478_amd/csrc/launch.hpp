@@ -34,7 +34,8 @@ hipError_t launch_oe_tensor(double* out, const Geom& g, const GLTable& gl, const
 hipError_t launch_pair_tensor(double2* out, const PairGeom& pg, const GLTable& gl, hipStream_t s);
 hipError_t launch_fft64(double2* data, int logN, long long es, long long ls, int lpb, long long bstride, int nlines,
                         const double2* tw64, hipStream_t s);
-hipError_t launch_pair_pack(const double2* in, float2* K, int Nx, int Ny, int Kx, double scale, hipStream_t s);
+hipError_t launch_pair_pack(const double2* in, float* K, int Nx, int Ny, int Kx, double scale, int parity,
+                            hipStream_t s);
 hipError_t launch_llg_stage(const LlgArgs& a, hipStream_t s);
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 

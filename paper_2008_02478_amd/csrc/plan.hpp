@@ -143,10 +143,15 @@ struct LayerArgs {
 };
 
 struct CoupleArgs {
-  float2* S; const float2* K;  // S[c][p][kx][ky], K[pair][component][kx][ky]
+  float2* S;                   // S[c][p][kx][ky]
+  const float* K;              // pair spectra, pair after pair (p <= q): [component][kx][ky]
   const PlaneInfo* pl;
   int Kx, NY, Nx;
   double* epart;               // per workgroup and plane, or nullptr
+  // bit i set: pair i has no in-plane centre offset, so each component of its
+  // spectrum is purely real (xx yy zz xy) or purely imaginary (xz yz) and is
+  // stored as one float per frequency; other pairs store complex values
+  unsigned long long parity_pairs;
 };
 
 struct FwdArgs {
