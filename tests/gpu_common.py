@@ -29,5 +29,14 @@ def rel_l2(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
+def max_cell(a, b):
+    """Largest per-cell error, max over cells of |a - b| (the 3-vector norm),
+    relative to the largest cell value max |b|: a point-wise check beside
+    the aggregate rel-L2."""
+    a = np.asarray(a, np.float64).reshape(3, -1)
+    b = np.asarray(b, np.float64).reshape(3, -1)
+    return float(np.max(np.linalg.norm(a - b, axis=0)) / np.max(np.linalg.norm(b, axis=0)))
+
+
 def to_dev(x, torch):
     return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")

@@ -10,7 +10,7 @@ import pytest
 from oracle import conv
 from oracle.newell import tensor_full
 from paper_2008_02478_amd import inputs
-from tests.gpu_common import TOL, rel_l2, require_gpu, say, to_dev
+from tests.gpu_common import TOL, max_cell, rel_l2, require_gpu, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -41,6 +41,7 @@ def test_c1_against_direct_sum(torch):
     say(f"  rel-L2 vs direct sum {rel_l2(H, Hd):.2e}, oracle routes differ by {rel_l2(Hf, Hd):.1e}")
     assert rel_l2(Hf, Hd) < 1e-12
     assert rel_l2(H, Hd) < TOL
+    assert max_cell(H, Hd) < TOL
     assert abs(E - conv.energy(M, Hd, h)) < TOL * abs(conv.energy(M, Hd, h))
 
 
@@ -64,8 +65,9 @@ def test_ragged_meshes(torch, n, h):
     Hr = conv.fft_conv(M, h)
     err = rel_l2(H, Hr)
     Er = conv.energy(M, Hr, h)
-    say(f"  rel-L2 {err:.2e}  energy rel {abs(E - Er) / abs(Er):.2e}")
+    say(f"  rel-L2 {err:.2e}  max cell {max_cell(H, Hr):.2e}  energy rel {abs(E - Er) / abs(Er):.2e}")
     assert err < TOL
+    assert max_cell(H, Hr) < TOL
     assert abs(E - Er) < TOL * abs(Er)
 
 
@@ -92,6 +94,7 @@ def test_c4_field_energy_and_gradients(torch):
             rel_l2(grad.cpu().numpy(), gr))
     say("  rel-L2 H %.2e  E(parseval) %.2e  E(cells) %.2e  grad %.2e" % errs)
     assert all(e < TOL for e in errs)
+    assert max_cell(H.cpu().numpy(), Hr) < TOL and max_cell(grad.cpu().numpy(), gr) < TOL
 
 
 @pytest.mark.parametrize("core,seed", [(1, 2), (-1, 3)])
@@ -103,8 +106,8 @@ def test_c2_vortex_field_and_energy(torch, core, seed):
     M = Ms * m.astype(np.float64)
     Hr = conv.fft_conv(M, h)
     Er = conv.energy(M, Hr, h)
-    say(f"  rel-L2 {rel_l2(H, Hr):.2e}  energy rel {abs(E - Er) / Er:.2e}")
-    assert rel_l2(H, Hr) < TOL
+    say(f"  rel-L2 {rel_l2(H, Hr):.2e}  max cell {max_cell(H, Hr):.2e}  energy rel {abs(E - Er) / Er:.2e}")
+    assert rel_l2(H, Hr) < TOL and max_cell(H, Hr) < TOL
     assert abs(E - Er) < TOL * Er
 
 
