@@ -169,26 +169,27 @@ constexpr int stage_table_size() {
   return n;
 }
 
-// Fill the table cooperatively from the FP32 W_4096 table (threads nth).
+// Fill the table cooperatively from the FP32 W_4096 table (threads nth).  The
+// stages are walked at compile time, so each entry costs a shift, a mask and
+// one table read.
+template <int M, int R, int NS, int OFF>
+__device__ __forceinline__ void fill_stage_table_from(float2* __restrict__ tab, const float2* __restrict__ tw,
+                                                      int tid, int nth) {
+  if constexpr (NS < M) {
+    constexpr int left = M / NS;
+    constexpr int RS = left >= R ? R : left;
+    constexpr int CNT = (RS - 1) * NS;
+    for (int e = tid; e < CNT; e += nth) {
+      const int r = e / NS + 1, k = e % NS;      // NS a power of two: shift and mask
+      tab[OFF + e] = twiddle<false>(tw, r * k, ilog2(NS * RS));
+    }
+    fill_stage_table_from<M, R, NS * RS, OFF + CNT>(tab, tw, tid, nth);
+  }
+}
 template <int M, int R>
 __device__ __forceinline__ void fill_stage_table(float2* __restrict__ tab, const float2* __restrict__ tw, int tid,
                                                  int nth) {
-  constexpr int N = stage_table_size<M, R>();
-  for (int e = tid; e < N; e += nth) {
-    int ns = R, off = 0, q = e;
-    while (true) {
-      const int left = M / ns, rs = left >= R ? R : left;
-      const int cnt = (rs - 1) * ns;
-      if (q < cnt) {
-        const int r = q / ns + 1, k = q % ns;
-        tab[off + q] = twiddle<false>(tw, r * k, ilog2(ns * rs));
-        break;
-      }
-      q -= cnt;
-      off += cnt;
-      ns *= rs;
-    }
-  }
+  fill_stage_table_from<M, R, R, 0>(tab, tw, tid, nth);
 }
 
 // One Stockham stage (not the first): NS = product of earlier radices, RS = this radix.

@@ -532,6 +532,8 @@ __global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_e
   float2* const tab = smem_base;
   float2* const smem = smem_base + xtab_points<LNX>();
 
+  // the x transform's twiddle table first, so its reads overlap the z phase
+  if constexpr (NX >= 4) fill_x_tables<LNX, INV_THREADS>(tab, a.tw, tid);
   // inverse z per (y, kx), keeping z < nz: the even kz residue, then the
   // odd one added through LDS (one residue live at a time)
   const int items = yg * Kx;
@@ -605,7 +607,7 @@ __global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_e
     }
   } else {
     const float beta = (a.scale_out && a.beta_ptr) ? (float)(a.beta_scale * *a.beta_ptr) : 0.f;
-    xinv_rows<LNX, INV_THREADS>(smem, tab, a.tw, rows, PITCH, [&](int row, int mm, float2 uu) {
+    xinv_rows<LNX, INV_THREADS, true>(smem, tab, a.tw, rows, PITCH, [&](int row, int mm, float2 uu) {
       const int yl = row / nz, z = row - yl * nz;
       const size_t off = ((size_t)z * ny + (y0 + yl)) * nx;
       float* dst = a.H + cbase + off;

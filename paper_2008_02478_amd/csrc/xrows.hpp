@@ -97,9 +97,18 @@ __device__ __forceinline__ void xfwd_rows(float2* __restrict__ smem, float2* __r
   }
 }
 
+// The stage table of the x passes' Nx/4-point residue FFTs.
+template <int LNX, int NTH>
+__device__ __forceinline__ void fill_x_tables(float2* __restrict__ tab, const float2* __restrict__ tw, int tid) {
+  constexpr int P = (1 << LNX) / 4;
+  fill_stage_table<P, LineShape<P>::R>(tab, tw, tid, NTH);
+}
+
 // Rows of smem hold X[0..L]; store(row, m, (x[2m], x[2m+1])) receives the
 // unnormalized inverse for m < NX/4.  Ends with a workgroup barrier.
-template <int LNX, int NTH, typename Store>
+// tables_ready: the caller filled the stage table earlier (fill_x_tables), so
+// its latency overlapped other work.
+template <int LNX, int NTH, bool TABLES_READY = false, typename Store>
 __device__ __forceinline__ void xinv_rows(float2* __restrict__ smem, float2* __restrict__ tab,
                                           const float2* __restrict__ tw, int rows, int pitch, Store&& store) {
   constexpr int NX = 1 << LNX;
@@ -112,7 +121,7 @@ __device__ __forceinline__ void xinv_rows(float2* __restrict__ smem, float2* __r
   const int sub = tid / (2 * T);
   const int r = (tid / T) & 1;
   const int t = tid % T;
-  fill_stage_table<P, R>(tab, tw, tid, NTH);
+  if constexpr (!TABLES_READY) fill_stage_table<P, R>(tab, tw, tid, NTH);
   const float2 rbase = twiddle<false>(tw, t, ilog2(2 * P));
   __syncthreads();
   for (int start = 0; start < rows; start += RPR) {
