@@ -95,6 +95,17 @@ __device__ __forceinline__ float2 tw_const(float2 a) {
   }
 }
 
+// f(i, base W_LEN^i) for i = 0 .. N-1 (forward, or the conjugate factors for
+// INV), the factors compile-time constants: the twiddles of points spaced
+// LEN-th of a turn apart from one table read.
+template <int LEN, int N, bool INV, int I = 0, typename F>
+__device__ __forceinline__ void for_const_twiddles(float2 base, F&& f) {
+  if constexpr (I < N) {
+    f(I, tw_const<LEN, I, INV>(base));
+    for_const_twiddles<LEN, N, INV, I + 1>(base, f);
+  }
+}
+
 template <int R>
 __device__ __forceinline__ constexpr int bitrev(int i) {
   int r = 0;
@@ -191,6 +202,74 @@ __device__ __forceinline__ void fill_stage_table(float2* __restrict__ tab, const
                                                  int nth) {
   fill_stage_table_from<M, R, R, 0>(tab, tw, tid, nth);
 }
+
+// The same tables (stage table and, if RES, the odd-residue table rtab of
+// fill_residue_table) staged through registers: load() issues the reads of the
+// W_4096 table, store() writes LDS.  A kernel issues load() before its bulk
+// loads and store() after them, so the table reads overlap them; memory
+// counters retire in issue order, so store() waits only for the table reads.
+// Lanes past an entry count read an in-range table entry (indices are masked)
+// and store it to a discard slot, so that no store is conditional (a
+// conditional store would let the compiler sink the read next to it, where
+// it is waited for at once).  NTH: threads of the workgroup (compile time).
+template <int M, int R, int NTH, bool RES>
+struct TabRegs {
+  template <int NS>
+  static constexpr int iters_from() {
+    if constexpr (NS >= M) {
+      return 0;
+    } else {
+      constexpr int left = M / NS, RS = left >= R ? R : left, CNT = (RS - 1) * NS;
+      return (CNT + NTH - 1) / NTH + iters_from<NS * RS>();
+    }
+  }
+  static constexpr int NRI = RES ? (M + NTH - 1) / NTH : 0;
+  static constexpr int K = iters_from<R>() + NRI;
+  float2 v[K > 0 ? K : 1];
+
+  template <int NS, int SLOT>
+  __device__ __forceinline__ void load_from(const float2* __restrict__ tw, int tid) {
+    if constexpr (NS < M) {
+      constexpr int left = M / NS, RS = left >= R ? R : left, CNT = (RS - 1) * NS, IT = (CNT + NTH - 1) / NTH;
+#pragma unroll
+      for (int i = 0; i < IT; ++i) {
+        const int e = tid + i * NTH;
+        v[SLOT + i] = twiddle<false>(tw, (e / NS + 1) * (e % NS), ilog2(NS * RS));
+      }
+      load_from<NS * RS, SLOT + IT>(tw, tid);
+    }
+  }
+  template <int NS, int SLOT, int OFF>
+  __device__ __forceinline__ void store_from(float2* __restrict__ tab, float2* sink, int tid) const {
+    if constexpr (NS < M) {
+      constexpr int left = M / NS, RS = left >= R ? R : left, CNT = (RS - 1) * NS, IT = (CNT + NTH - 1) / NTH;
+#pragma unroll
+      for (int i = 0; i < IT; ++i) {
+        const int e = tid + i * NTH;
+        *((CNT % NTH == 0 || e < CNT) ? tab + OFF + e : sink) = v[SLOT + i];
+      }
+      store_from<NS * RS, SLOT + IT, OFF + CNT>(tab, sink, tid);
+    }
+  }
+  __device__ __forceinline__ void load(const float2* __restrict__ tw, int tid) {
+    load_from<R, 0>(tw, tid);
+    if constexpr (RES) {
+#pragma unroll
+      for (int i = 0; i < NRI; ++i) v[K - NRI + i] = twiddle<false>(tw, tid + i * NTH, ilog2(2 * M));
+    }
+  }
+  __device__ __forceinline__ void store(float2* __restrict__ tab, float2* __restrict__ rtab, int tid) const {
+    __shared__ float2 sink;   // written by lanes past an entry count, never read
+    store_from<R, 0, 0>(tab, &sink, tid);
+    if constexpr (RES) {
+#pragma unroll
+      for (int i = 0; i < NRI; ++i) {
+        const int k = tid + i * NTH;
+        *((M % NTH == 0 || k < M) ? rtab + k : &sink) = v[K - NRI + i];
+      }
+    }
+  }
+};
 
 // One Stockham stage (not the first): NS = product of earlier radices, RS = this radix.
 template <int M, int R, int NS, int RS, bool INV, int OFF>

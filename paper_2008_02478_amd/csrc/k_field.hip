@@ -67,29 +67,46 @@ __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_e
       smem[row * PITCH] = make_float2(v, 0.f);
     }
   } else {
-    const bool even = (nx & 1) == 0;
     const float* const mc = a.m + (size_t)c * nz * ny * nx;
-    xfwd_rows<LNX, FWD_THREADS>(smem, tab, a.tw, rows, PITCH, [&](int row, int mm) -> float2 {
+    // row offsets of the mesh arrays
+    auto roff = [&](int row) -> size_t {
       const int yl = row / nz, z = row - yl * nz;
-      const float* src = mc + ((size_t)z * ny + (y0 + yl)) * nx;
+      return ((size_t)z * ny + (y0 + yl)) * nx;
+    };
+    // loads read in-range memory for every m (indices past the row clamp to
+    // its start); the scale step zeroes what lies past nx
+    auto scale = [&](int row, int mm, float2 v) -> float2 {
       const int xi = 2 * mm;
-      if (even) return xi < nx ? reinterpret_cast<const float2*>(src)[mm] : make_float2(0.f, 0.f);
-      return make_float2(xi < nx ? src[xi] : 0.f, xi + 1 < nx ? src[xi + 1] : 0.f);
-    }, [&](int row, int mm, float2 v) -> float2 {
+      const bool in0 = xi < nx, in1 = xi + 1 < nx;
       if (a.m2) {
         // two sublattices: (ms m + ms2 m2) / 2, the second read here
-        const int yl = row / nz, z = row - yl * nz;
-        const float* src2 = a.m2 + (size_t)c * nz * ny * nx + ((size_t)z * ny + (y0 + yl)) * nx;
-        const int xi = 2 * mm;
-        const float w0 = xi < nx ? src2[xi] : 0.f, w1 = xi + 1 < nx ? src2[xi + 1] : 0.f;
-        return make_float2(0.5f * (a.ms * v.x + a.ms2 * w0), 0.5f * (a.ms * v.y + a.ms2 * w1));
+        const float* src2 = a.m2 + (size_t)c * nz * ny * nx + roff(row);
+        const float w0 = src2[in0 ? xi : 0], w1 = src2[in1 ? xi + 1 : 0];
+        return make_float2(in0 ? 0.5f * (a.ms * v.x + a.ms2 * w0) : 0.f,
+                           in1 ? 0.5f * (a.ms * v.y + a.ms2 * w1) : 0.f);
       }
-      if (!a.Ms) return make_float2(v.x * a.ms, v.y * a.ms);
-      const int yl = row / nz, z = row - yl * nz;
-      const float* msr = a.Ms + ((size_t)z * ny + (y0 + yl)) * nx;
-      const int xi = 2 * mm;
-      return make_float2(xi < nx ? v.x * msr[xi] : 0.f, xi + 1 < nx ? v.y * msr[xi + 1] : 0.f);
-    });
+      if (!a.Ms) return make_float2(in0 ? v.x * a.ms : 0.f, in1 ? v.y * a.ms : 0.f);
+      const float* msr = a.Ms + roff(row);
+      const float s0 = msr[in0 ? xi : 0], s1 = msr[in1 ? xi + 1 : 0];
+      return make_float2(in0 ? v.x * s0 : 0.f, in1 ? v.y * s1 : 0.f);
+    };
+    if ((nx & 1) == 0 && !a.m2 && !a.Ms) {
+      // the common case, branch-free: even rows start 8-byte aligned (one
+      // 8-byte load per point), one saturation for the whole mesh
+      const float ms = a.ms;
+      xfwd_rows<LNX, FWD_THREADS>(smem, tab, a.tw, rows, PITCH, [&](int row, int mm) -> float2 {
+        const float2* src = reinterpret_cast<const float2*>(mc + roff(row));
+        return src[2 * mm < nx ? mm : 0];
+      }, [&](int, int mm, float2 v) -> float2 {
+        return 2 * mm < nx ? make_float2(v.x * ms, v.y * ms) : make_float2(0.f, 0.f);
+      });
+    } else {
+      xfwd_rows<LNX, FWD_THREADS>(smem, tab, a.tw, rows, PITCH, [&](int row, int mm) -> float2 {
+        const float* src = mc + roff(row);
+        const int xi = 2 * mm;
+        return make_float2(src[xi < nx ? xi : 0], src[xi + 1 < nx ? xi + 1 : 0]);
+      }, scale);
+    }
   }
   __syncthreads();
 
@@ -246,9 +263,6 @@ k_mid(MidArgs a) {
   const size_t cstride = (size_t)a.Nz * a.nTiles * ny * TILE;
   float2* blk0 = a.T + ((size_t)kz * a.nTiles + tile) * ny * TILE + half * KW;
 
-  if constexpr (M > R) fill_stage_table<M, R>(tab, a.tw, tid, blockDim.x);
-  if constexpr (NRES == 2) fill_residue_table<M>(rtab, a.tw, tid, blockDim.x);
-
   // The kernel spectrum of this workgroup (KW consecutive kx lines of NKC rows
   // of KYP floats, contiguous in K[kz][kx][c][ky], plus their NKC KW Nyquist
   // entries) is requested with the components and held in registers through
@@ -265,13 +279,15 @@ k_mid(MidArgs a) {
   const int kx0 = tile * TILE + half * KW;
   float4 kp[KIT];
   float knv = 0.f;
-  __syncthreads();   // stage table complete before any FFT reads it
   float2 v[3][R];
   // S index of (c, kz, kx, residue r, k') in MODE 1 / 2
   auto sidx = [&](int c, int j) -> size_t {
     return (((size_t)c * a.Nz + kz) * a.Kx + kx) * NY + (size_t)r * M + (t + T * j);
   };
   if constexpr (MODE == 2) {
+    if constexpr (M > R) fill_stage_table<M, R>(tab, a.tw, tid, NTHK);
+    if constexpr (NRES == 2) fill_residue_table<M>(rtab, a.tw, tid, NTHK);
+    __syncthreads();   // tables complete before any transform reads them
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -285,30 +301,41 @@ k_mid(MidArgs a) {
     constexpr int NTH = mid_threads(LNY, KW, R);
     constexpr int ITER = (NYMAX * V + NTH - 1) / NTH;
     const int nv = ny * V;
+    // twiddle-table reads first, written to LDS once the bulk loads are issued
+    TabRegs<M, R, NTHK, NRES == 2> tabr;
+    tabr.load(a.tw, tid);
     float4 pre[3][ITER];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const float4* b4 = reinterpret_cast<const float4*>(blk0 + c * cstride);
 #pragma unroll
       for (int i = 0; i < ITER; ++i) {
+        // unconditional (rows past ny read row 0 and are zeroed when staged),
+        // so that the waits for these loads count exactly
         const int e = tid + i * NTH;
-        const int y = e / V, q = e - y * V;
-        pre[c][i] = e < nv ? b4[(unsigned)y * (TILE / 2) + q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const int y = e < nv ? e / V : 0, q = e < nv ? e - y * V : 0;
+        pre[c][i] = b4[(unsigned)y * (TILE / 2) + q];
       }
     }
     // kernel rows after the components: waits for the components then leave
     // the kernel rows in flight (memory counters retire in issue order)
     if constexpr (PROD) {
       const float4* Kb4 = reinterpret_cast<const float4*>(a.K + ((size_t)kzf * a.Kx + kx0) * NKC * KYP);
+      // unconditional loads (rows past the block read its first float4,
+      // which exists), so that no moves of a loaded value sit right behind
+      // its load; entries out of range are dropped as they move to LDS
 #pragma unroll
       for (int i = 0; i < KIT; ++i) {
         const int e = tid + i * NTHK;
         const bool in = e < KF4 && kx0 + e / (NKC * KYP / 4) < a.Kx;
-        kp[i] = in ? Kb4[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+        kp[i] = Kb4[in ? e : 0];
       }
-      if (NY >= 4 && tid < NKC * KW && kx0 + tid / NKC < a.Kx)
-        knv = a.K[(size_t)NKC * a.Kzh * a.Kx * KYP + ((size_t)kzf * a.Kx + kx0) * NKC + tid];
+      if constexpr (NY >= 4) {
+        const bool in = tid < NKC * KW && kx0 + tid / NKC < a.Kx;
+        knv = a.K[(size_t)NKC * a.Kzh * a.Kx * KYP + ((size_t)kzf * a.Kx + kx0) * NKC + (in ? tid : 0)];
+      }
     }
+    tabr.store(tab, rtab, tid);   // read by the transforms after the staging barrier
     // all M rows staged (rows past ny were loaded as zeros), so the reads
     // below need no bounds and their offsets are compile-time constants
 #pragma unroll
@@ -319,8 +346,9 @@ k_mid(MidArgs a) {
         if ((NYMAX * V) % NTH == 0 || e < NYMAX * V) {
           const int y = e / V, q = e - y * V;
           float2* const d = stage + c * CST + y * KWP + 2 * q;
-          d[0] = make_float2(pre[c][i].x, pre[c][i].y);
-          d[1] = make_float2(pre[c][i].z, pre[c][i].w);
+          const float4 p4 = e < nv ? pre[c][i] : make_float4(0.f, 0.f, 0.f, 0.f);
+          d[0] = make_float2(p4.x, p4.y);
+          d[1] = make_float2(p4.z, p4.w);
         }
       }
     }
@@ -369,19 +397,21 @@ k_mid(MidArgs a) {
       const int e = tid + i * NTHK;
       if (e < KF4) {
         const int row = (4 * e) / KYP, ky0 = 4 * e - row * KYP;
-        if ((ZODD >> (row % NKC)) & 1u) {
-          kp[i].x *= sz; kp[i].y *= sz; kp[i].z *= sz; kp[i].w *= sz;
-        }
+        // sign of the rows odd in z, zero for kx lines past the spectrum
+        const float f = kx0 + e / (NKC * KYP / 4) >= a.Kx ? 0.f : ((ZODD >> (row % NKC)) & 1u) ? sz : 1.f;
         float* const dst = kl + row * KLP;
         if constexpr (NRES == 2) {
-          *reinterpret_cast<float2*>(dst + ky0 / 2) = make_float2(kp[i].x, kp[i].z);
-          *reinterpret_cast<float2*>(dst + OH + ky0 / 2) = make_float2(kp[i].y, kp[i].w);
+          dst[ky0 / 2] = f * kp[i].x;
+          dst[ky0 / 2 + 1] = f * kp[i].z;
+          dst[OH + ky0 / 2] = f * kp[i].y;
+          dst[OH + ky0 / 2 + 1] = f * kp[i].w;
         } else {
-          *reinterpret_cast<float4*>(dst + ky0) = kp[i];
+          *reinterpret_cast<float4*>(dst + ky0) = make_float4(f * kp[i].x, f * kp[i].y, f * kp[i].z, f * kp[i].w);
         }
       }
     }
-    if (NY >= 4 && tid < NKC * KW) kl[tid * KLP + KYP / 2] = ((ZODD >> (tid % NKC)) & 1u) ? sz * knv : knv;
+    if (NY >= 4 && tid < NKC * KW)
+      kl[tid * KLP + KYP / 2] = kx0 + tid / NKC >= a.Kx ? 0.f : ((ZODD >> (tid % NKC)) & 1u) ? sz * knv : knv;
     __syncthreads();
   }
   double e = 0.0;
@@ -532,8 +562,10 @@ __global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_e
   float2* const tab = smem_base;
   float2* const smem = smem_base + xtab_points<LNX>();
 
-  // the x transform's twiddle table first, so its reads overlap the z phase
-  if constexpr (NX >= 4) fill_x_tables<LNX, INV_THREADS>(tab, a.tw, tid);
+  // the x transform's twiddle tables first, so that their reads overlap the
+  // z phase (stored to LDS after it)
+  XTabPre<(NX >= 4 ? LNX : 2), INV_THREADS> xpre;
+  if constexpr (NX >= 4) xpre.load(a.tw, tid);
   // inverse z per (y, kx), keeping z < nz: the even kz residue, then the
   // odd one added through LDS (one residue live at a time)
   const int items = yg * Kx;
@@ -607,7 +639,8 @@ __global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_e
     }
   } else {
     const float beta = (a.scale_out && a.beta_ptr) ? (float)(a.beta_scale * *a.beta_ptr) : 0.f;
-    xinv_rows<LNX, INV_THREADS, true>(smem, tab, a.tw, rows, PITCH, [&](int row, int mm, float2 uu) {
+    xpre.store(tab, tid);
+    xinv_rows_pre<LNX, INV_THREADS>(smem, tab, a.tw, rows, PITCH, xpre, [&](int row, int mm, float2 uu) {
       const int yl = row / nz, z = row - yl * nz;
       const size_t off = ((size_t)z * ny + (y0 + yl)) * nx;
       float* dst = a.H + cbase + off;
