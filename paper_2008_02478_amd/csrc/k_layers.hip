@@ -101,51 +101,84 @@ __device__ __forceinline__ void sym_mac(float2 (&h)[3], const float2 (&k)[6], co
   h[2] = cadd(h[2], cadd(mul(k[4], m[0]), cadd(mul(k[5], m[1]), mul(k[2], m[2]))));
 }
 
+// plane pair n of the order (0,0), (0,1) .. (0,P-1), (1,1) .. (P-1,P-1)
 template <int P>
-__global__ void __launch_bounds__(256) k_couple(CoupleArgs a) {
+constexpr int pair_p(int n) {
+  int p = 0;
+  while (n >= P - p) { n -= P - p; ++p; }
+  return p;
+}
+template <int P>
+constexpr int pair_q(int n) {
+  int p = 0;
+  while (n >= P - p) { n -= P - p; ++p; }
+  return p + n;
+}
+
+// One pair's spectrum for this point as raw words: a pair stored one float
+// per component (parity) reads that float twice; a full pair reads the real
+// and imaginary words.  Branch-free, so that the next pair's reads can be in
+// flight while this pair is summed.
+struct PairWords {
+  float x[6], y[6];
+};
+__device__ __forceinline__ void load_pair(PairWords& w, const float* __restrict__ K, size_t koff, bool par,
+                                          size_t npt, size_t pt) {
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const size_t i = (size_t)e * npt + pt;
+    const float* const ax = K + koff + (par ? i : 2 * i);
+    w.x[e] = ax[0];
+    w.y[e] = ax[par ? 0 : 1];
+  }
+}
+
+template <int P, int N>
+__device__ __forceinline__ void couple_pairs(const CoupleArgs& a, size_t npt, size_t pt, size_t koff,
+                                             PairWords& cur, PairWords& nxt, float2 (&M)[P][3],
+                                             float2 (&H)[P][3], const float (&vol)[P]) {
+  constexpr int NP = P * (P + 1) / 2;
+  if constexpr (N < NP) {
+    constexpr int p = pair_p<P>(N), q = pair_q<P>(N);
+    const bool par = (a.parity_pairs >> N) & 1ull;
+    const size_t knext = koff + (size_t)(par ? 6 : 12) * npt;
+    // the next pair's words are requested before this pair is summed
+    if constexpr (N + 1 < NP) load_pair(nxt, a.K, knext, (a.parity_pairs >> (N + 1)) & 1ull, npt, pt);
+    float2 k6[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      // parity pairs: real xx yy zz xy, imaginary xz yz
+      if (e < 4) k6[e] = make_float2(cur.x[e], par ? 0.f : cur.y[e]);
+      else k6[e] = make_float2(par ? 0.f : cur.x[e], cur.y[e]);
+    }
+    sym_mac(H[p], k6, M[q], 1.f, false);
+    if constexpr (q != p) sym_mac(H[q], k6, M[p], vol[p] / vol[q], true);
+    couple_pairs<P, N + 1>(a, npt, pt, knext, nxt, cur, M, H, vol);
+  }
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 6 ? 4 : 2, 8))) k_couple(CoupleArgs a) {
   __shared__ double red[4][P];
   const size_t npt = (size_t)a.Kx * a.NY;
   const size_t pt = (size_t)blockIdx.x * 256 + threadIdx.x;
   const bool act = pt < npt;
+  const size_t ptc = act ? pt : 0;          // lanes past the end read point 0
   const int kx = act ? (int)(pt / a.NY) : 0;
   float2 M[P][3], H[P][3];
   float vol[P];
+  PairWords wa, wb;
+  load_pair(wa, a.K, 0, a.parity_pairs & 1ull, npt, ptc);
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     vol[p] = a.pl[p].vol;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      M[p][c] = act ? a.S[((size_t)c * P + p) * npt + pt] : make_float2(0.f, 0.f);
+      M[p][c] = a.S[((size_t)c * P + p) * npt + ptc];
       H[p][c] = make_float2(0.f, 0.f);
     }
   }
-  int pair = 0;
-  size_t koff = 0;   // float offset of the pair's spectrum
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-#pragma unroll
-    for (int q = p; q < P; ++q) {
-      float2 k6[6];
-      if ((a.parity_pairs >> pair) & 1ull) {
-        // real xx yy zz xy, imaginary xz yz: one float each
-        const float* const kr = a.K + koff;
-#pragma unroll
-        for (int e = 0; e < 6; ++e) {
-          const float v = act ? kr[(size_t)e * npt + pt] : 0.f;
-          k6[e] = e < 4 ? make_float2(v, 0.f) : make_float2(0.f, v);
-        }
-        koff += (size_t)6 * npt;
-      } else {
-        const float2* const kc = reinterpret_cast<const float2*>(a.K + koff);
-#pragma unroll
-        for (int e = 0; e < 6; ++e) k6[e] = act ? kc[(size_t)e * npt + pt] : make_float2(0.f, 0.f);
-        koff += (size_t)12 * npt;
-      }
-      sym_mac(H[p], k6, M[q], 1.f, false);
-      if (q != p) sym_mac(H[q], k6, M[p], vol[p] / vol[q], true);
-      ++pair;
-    }
-  }
+  couple_pairs<P, 0>(a, npt, ptc, 0, wa, wb, M, H, vol);
   if (act) {
 #pragma unroll
     for (int p = 0; p < P; ++p)
