@@ -18,6 +18,7 @@
 #include "fft_core.hpp"
 #include "plan.hpp"
 #include "xrows.hpp"
+#include "reduce.hpp"
 
 namespace demag {
 
@@ -188,18 +189,6 @@ template <int M, int NRES>
 constexpr int mid_rtab_points() { return NRES == 2 ? ((M + 31) / 32) * 32 : 0; }
 constexpr int mid_threads(int lny, int kw, int r) { return mid_threads_rt(lny > 0 ? (1 << lny) / 2 : 1, kw, r); }
 
-template <typename Tv>
-__device__ __forceinline__ Tv block_sum(Tv v, Tv* red) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[w] = v;
-  __syncthreads();
-  Tv s = 0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
-  return s;
-}
 
 // MODE 0: y FFT, kernel product, inverse y FFT (the pipelined pass).
 // MODE 1: y FFT only; spectra to S[c][kz][kx][ky] with ky ordered by residue
@@ -664,14 +653,22 @@ __global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_e
 // Sum of the middle pass' Parseval partials in a fixed order:
 // E = scale * sum(partials), scale = -(mu0/2) V.
 // One workgroup per batch member; out index gid[member] (or the member).
-__global__ void __launch_bounds__(RED_THREADS) k_energy_final(const double* part, int n, double scale,
-                                                              double* out, const int* gid) {
-  __shared__ double red[RED_THREADS / 64];
+__global__ void __launch_bounds__(FINAL_THREADS) k_energy_final(const double* part, int n, double scale,
+                                                                double* out, const int* gid) {
+  __shared__ double red[FINAL_THREADS / 64];
   const int b = blockIdx.x;
   part += (size_t)b * n;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += RED_THREADS) s += part[i];
-  s = block_sum(s, red);
+  // four independent sums per thread, so that four reads are in flight
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = threadIdx.x;
+  for (; i + 3 * FINAL_THREADS < n; i += 4 * FINAL_THREADS) {
+    s0 += part[i];
+    s1 += part[i + FINAL_THREADS];
+    s2 += part[i + 2 * FINAL_THREADS];
+    s3 += part[i + 3 * FINAL_THREADS];
+  }
+  for (; i < n; i += FINAL_THREADS) s0 += part[i];
+  const double s = block_sum((s0 + s1) + (s2 + s3), red);
   if (threadIdx.x == 0) out[gid ? gid[b] : b] = scale * s;
 }
 
@@ -873,7 +870,7 @@ hipError_t launch_mid_split(const Geom& g, const MidArgs& a, int mode, hipStream
 
 hipError_t launch_energy_final(const double* part, int n, double scale, double* out, hipStream_t s, int nb,
                                const int* gid) {
-  hipLaunchKernelGGL(k_energy_final, dim3(nb), dim3(RED_THREADS), 0, s, part, n, scale, out, gid);
+  hipLaunchKernelGGL(k_energy_final, dim3(nb), dim3(FINAL_THREADS), 0, s, part, n, scale, out, gid);
   return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@
 #include "plan.hpp"
 #include "xrows.hpp"
 #include "launch.hpp"
+#include "reduce.hpp"
 
 namespace demag {
 
@@ -210,33 +211,38 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 6
 
 // energies of the meshes of a group: out[gid] = scale * sum over the mesh's
 // planes and all workgroups' partials (fixed order)
-__global__ void __launch_bounds__(RED_THREADS) k_lenergy(const double* part, int nblk, int P, const PlaneInfo* pl,
-                                                         double scale, double* out) {
-  __shared__ double red[RED_THREADS / 64];
+__global__ void __launch_bounds__(FINAL_THREADS) k_lenergy(const double* part, int nblk, int P, const PlaneInfo* pl,
+                                                           double scale, double* out) {
+  __shared__ double red[FINAL_THREADS / 64];
   __shared__ double tot[MAXP];
-  for (int p = 0; p < P; ++p) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += RED_THREADS) s += part[(size_t)i * P + p];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int w = 0; w < RED_THREADS / 64; ++w) t += red[w];
-      tot[p] = t;
+  __shared__ int gid[MAXP];
+  if ((int)threadIdx.x < P) gid[threadIdx.x] = pl[threadIdx.x].gid;
+  // every plane's partials of a workgroup entry at once (P contiguous words)
+  double acc[MAXP];
+#pragma unroll
+  for (int p = 0; p < MAXP; ++p) acc[p] = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += FINAL_THREADS) {
+#pragma unroll
+    for (int p = 0; p < MAXP; ++p)
+      if (p < P) acc[p] += part[(size_t)i * P + p];
+  }
+#pragma unroll
+  for (int p = 0; p < MAXP; ++p) {
+    if (p < P) {
+      const double t = block_sum(acc[p], red);
+      if (threadIdx.x == 0) tot[p] = t;
     }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int p = 0; p < P; ++p) {
       bool first = true;
-      for (int q = 0; q < p; ++q) first = first && pl[q].gid != pl[p].gid;
+      for (int q = 0; q < p; ++q) first = first && gid[q] != gid[p];
       if (!first) continue;
       double t = 0.0;
       for (int q = p; q < P; ++q)
-        if (pl[q].gid == pl[p].gid) t += tot[q];
-      out[pl[p].gid] = scale * t;
+        if (gid[q] == gid[p]) t += tot[q];
+      out[gid[p]] = scale * t;
     }
   }
 }
@@ -308,7 +314,7 @@ hipError_t launch_couple(int P, const CoupleArgs& a, hipStream_t s) {
 
 hipError_t launch_layer_energy(const double* part, int nblk, int P, const PlaneInfo* pl, double scale, double* out,
                                hipStream_t s) {
-  hipLaunchKernelGGL(k_lenergy, dim3(1), dim3(RED_THREADS), 0, s, part, nblk, P, pl, scale, out);
+  hipLaunchKernelGGL(k_lenergy, dim3(1), dim3(FINAL_THREADS), 0, s, part, nblk, P, pl, scale, out);
   return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@ constexpr int TILE = 16;         // kx points per tile of the spectrum work buff
 constexpr int FWD_THREADS = 512;
 constexpr int INV_THREADS = 512;
 constexpr int RED_THREADS = 256;
+constexpr int FINAL_THREADS = 1024;   // threads of the single-workgroup final reductions
 
 // Points per lane (R) of an M-point line FFT, and its padded LDS footprint
 // (one pad point after every 2^3 points for radix 8, 2^5 for radix 16).
