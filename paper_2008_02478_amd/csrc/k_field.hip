@@ -634,15 +634,27 @@ __global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_e
       const size_t off = ((size_t)z * ny + (y0 + yl)) * nx;
       float* dst = a.H + cbase + off;
       const int xi = 2 * mm;
+      // reads at clamped (in-range) indices, not under the bounds tests, so
+      // that they are not waited for one by one
+      const bool in0 = xi < nx, in1 = xi + 1 < nx;
+      const int x0 = in0 ? xi : 0, x1 = in1 ? xi + 1 : 0;
       float v0 = uu.x, v1 = uu.y;
       if (a.scale_out) {
-        const float* aux = a.aux + cbase + off;
-        const float* msr = a.Ms ? a.Ms + off : nullptr;
-        if (xi < nx) v0 = (msr ? msr[xi] : a.ms) * (v0 + (a.beta_ptr ? beta * aux[xi] : 0.f));
-        if (xi + 1 < nx) v1 = (msr ? msr[xi + 1] : a.ms) * (v1 + (a.beta_ptr ? beta * aux[xi + 1] : 0.f));
+        if (a.beta_ptr) {
+          const float* aux = a.aux + cbase + off;
+          v0 += beta * aux[x0];
+          v1 += beta * aux[x1];
+        }
+        const float s0 = a.Ms ? a.Ms[off + x0] : a.ms, s1 = a.Ms ? a.Ms[off + x1] : a.ms;
+        v0 *= s0;
+        v1 *= s1;
       }
-      if (xi < nx) dst[xi] = a.accumulate ? dst[xi] + v0 : v0;
-      if (xi + 1 < nx) dst[xi + 1] = a.accumulate ? dst[xi + 1] + v1 : v1;
+      if (a.accumulate) {
+        v0 += dst[x0];
+        v1 += dst[x1];
+      }
+      if (in0) dst[xi] = v0;
+      if (in1) dst[xi + 1] = v1;
     });
   }
 }

@@ -216,16 +216,20 @@ __global__ void __launch_bounds__(FINAL_THREADS) k_lenergy(const double* part, i
   __shared__ double red[FINAL_THREADS / 64];
   __shared__ double tot[MAXP];
   __shared__ int gid[MAXP];
-  if ((int)threadIdx.x < P) gid[threadIdx.x] = pl[threadIdx.x].gid;
   // every plane's partials of a workgroup entry at once (P contiguous words)
   double acc[MAXP];
 #pragma unroll
   for (int p = 0; p < MAXP; ++p) acc[p] = 0.0;
   for (int i = threadIdx.x; i < nblk; i += FINAL_THREADS) {
+    // unconditional reads (slots past P re-read plane 0), so that all are in
+    // flight at once
+    double v[MAXP];
 #pragma unroll
-    for (int p = 0; p < MAXP; ++p)
-      if (p < P) acc[p] += part[(size_t)i * P + p];
+    for (int p = 0; p < MAXP; ++p) v[p] = part[(size_t)i * P + (p < P ? p : 0)];
+#pragma unroll
+    for (int p = 0; p < MAXP; ++p) acc[p] += p < P ? v[p] : 0.0;
   }
+  if ((int)threadIdx.x < P) gid[threadIdx.x] = pl[threadIdx.x].gid;   // published by the barriers below
 #pragma unroll
   for (int p = 0; p < MAXP; ++p) {
     if (p < P) {
