@@ -17,7 +17,6 @@
 #include "plan.hpp"
 #include "xrows.hpp"
 #include "launch.hpp"
-#include "reduce.hpp"
 
 namespace demag {
 
@@ -213,7 +212,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 6
 // planes and all workgroups' partials (fixed order)
 __global__ void __launch_bounds__(FINAL_THREADS) k_lenergy(const double* part, int nblk, int P, const PlaneInfo* pl,
                                                            double scale, double* out) {
-  __shared__ double red[FINAL_THREADS / 64];
+  constexpr int NW = FINAL_THREADS / 64;
+  __shared__ double red[NW][MAXP];
   __shared__ double tot[MAXP];
   __shared__ int gid[MAXP];
   // every plane's partials of a workgroup entry at once (P contiguous words)
@@ -229,13 +229,24 @@ __global__ void __launch_bounds__(FINAL_THREADS) k_lenergy(const double* part, i
 #pragma unroll
     for (int p = 0; p < MAXP; ++p) acc[p] += p < P ? v[p] : 0.0;
   }
-  if ((int)threadIdx.x < P) gid[threadIdx.x] = pl[threadIdx.x].gid;   // published by the barriers below
+  if ((int)threadIdx.x < P) gid[threadIdx.x] = pl[threadIdx.x].gid;
+  // all planes' wavefront sums together (independent butterflies), then the
+  // wavefronts in order
 #pragma unroll
-  for (int p = 0; p < MAXP; ++p) {
-    if (p < P) {
-      const double t = block_sum(acc[p], red);
-      if (threadIdx.x == 0) tot[p] = t;
-    }
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int p = 0; p < MAXP; ++p) acc[p] += __shfl_xor(acc[p], o);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int p = 0; p < MAXP; ++p) red[w][p] = acc[p];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < P) {
+    double t = 0.0;
+    for (int i = 0; i < NW; ++i) t += red[i][threadIdx.x];
+    tot[threadIdx.x] = t;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
