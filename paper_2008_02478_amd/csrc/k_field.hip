@@ -131,38 +131,21 @@ __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_e
       }
     } else {
       constexpr int Q = NZ / 2;
-      if constexpr (NZ >= 128) {
-        // long z lines: one residue in registers at a time, the column read
-        // from LDS once per residue
-        const float2* const col = smem + (yl * nz) * PITCH + kx;
-        float2 v[Q];
-#pragma unroll
-        for (int z = 0; z < Q; ++z) v[z] = (z < nz) ? col[z * PITCH] : make_float2(0.f, 0.f);
-        dft<Q, false>(v);
-#pragma unroll
-        for (int k = 0; k < Q; ++k) Tc[o + (unsigned)(2 * k) * kzstride] = v[k];
-#pragma unroll
-        for (int z = 0; z < Q; ++z) v[z] = (z < nz) ? col[z * PITCH] : make_float2(0.f, 0.f);
-        zodd_twiddle<NZ, 0, false>(v);
-        dft<Q, false>(v);
-#pragma unroll
-        for (int k = 0; k < Q; ++k) Tc[o + (unsigned)(2 * k + 1) * kzstride] = v[k];
-      } else {
-      float2 xz[Q];
-#pragma unroll
-      for (int z = 0; z < Q; ++z)
-        xz[z] = (z < nz) ? smem[(yl * nz + z) * PITCH + kx] : make_float2(0.f, 0.f);
+      // one residue in registers at a time, the column read from LDS once
+      // per residue
+      const float2* const col = smem + (yl * nz) * PITCH + kx;
       float2 v[Q];
 #pragma unroll
-      for (int z = 0; z < Q; ++z) v[z] = xz[z];
+      for (int z = 0; z < Q; ++z) v[z] = (z < nz) ? col[z * PITCH] : make_float2(0.f, 0.f);
       dft<Q, false>(v);
 #pragma unroll
       for (int k = 0; k < Q; ++k) Tc[o + (unsigned)(2 * k) * kzstride] = v[k];
-      zodd_twiddle<NZ, 0, false>(xz);
-      dft<Q, false>(xz);
 #pragma unroll
-      for (int k = 0; k < Q; ++k) Tc[o + (unsigned)(2 * k + 1) * kzstride] = xz[k];
-      }
+      for (int z = 0; z < Q; ++z) v[z] = (z < nz) ? col[z * PITCH] : make_float2(0.f, 0.f);
+      zodd_twiddle<NZ, 0, false>(v);
+      dft<Q, false>(v);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) Tc[o + (unsigned)(2 * k + 1) * kzstride] = v[k];
     }
   }
 }
@@ -306,8 +289,9 @@ k_mid(MidArgs a) {
         pre[c][i] = b4[(unsigned)y * (TILE / 2) + q];
       }
     }
-    // kernel rows after the components: waits for the components then leave
-    // the kernel rows in flight (memory counters retire in issue order)
+    // kernel rows after the components: the staging below waits only for the
+    // components (memory counters retire in issue order) and the kernel rows
+    // stay in flight through the forward transforms
     if constexpr (PROD) {
       const float4* Kb4 = reinterpret_cast<const float4*>(a.K + ((size_t)kzf * a.Kx + kx0) * NKC * KYP);
       // unconditional loads (rows past the block read its first float4,
@@ -325,7 +309,7 @@ k_mid(MidArgs a) {
       }
     }
     tabr.store(tab, rtab, tid);   // read by the transforms after the staging barrier
-    // all M rows staged (rows past ny were loaded as zeros), so the reads
+    // all M rows staged (rows past ny as zeros), so the reads
     // below need no bounds and their offsets are compile-time constants
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
