@@ -20,6 +20,14 @@
 
 namespace demag {
 
+// Index of the fine-lattice offset i on a plane of stride s and n cells: i / s
+// when i is a non-negative multiple of s below s n, else -1.  The quotient is
+// the nearest integer to i (1/s), exact for |i| < 2^22 (no integer division).
+__device__ __forceinline__ int on_stride(int i, int s, int n) {
+  const int q = (int)rintf((float)i * __frcp_rn((float)s));
+  return (q * s == i && q >= 0 && q < n) ? q : -1;
+}
+
 template <int LNX>
 __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_eu(LNX >= 12 ? 2 : 4, 8))) k_lfwd(LayerArgs a) {
   extern __shared__ float2 smem_base[];
@@ -28,22 +36,24 @@ __global__ void __launch_bounds__(FWD_THREADS) __attribute__((amdgpu_waves_per_e
   float2* const smem = smem_base + xtab_points<LNX>();
   const int lg = xcd_logical(blockIdx.x, gridDim.x);
   const int c = lg / a.Ly, v = lg - c * a.Ly;
+  // A fine-lattice point (2 mm + h, v) holds a cell of plane p when it falls on
+  // the plane's stride inside its extent.  Loads read a clamped in-range cell
+  // and the scale step zeroes the points without one, so that no load sits
+  // under a condition (its wait would be taken at once).
+  auto cell_x = [&](const PlaneInfo& pi, int ix) -> int { return on_stride(ix, pi.sx, pi.nx); };
+  auto cell_y = [&](const PlaneInfo& pi) -> int { return on_stride(v - pi.oy, pi.sy, pi.ny); };
   xfwd_rows<LNX, FWD_THREADS>(smem, tab, a.tw, a.P, PITCH, [&](int p, int mm) -> float2 {
     const PlaneInfo pi = a.pl[p];
-    const int jy = v - pi.oy;
-    if (jy < 0 || jy % pi.sy != 0 || jy / pi.sy >= pi.ny) return make_float2(0.f, 0.f);
-    const float* src = a.m + pi.moff + (((size_t)c * pi.nz + pi.k) * pi.ny + jy / pi.sy) * pi.nx;
-    float val[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int ix = 2 * mm + h - pi.ox;
-      val[h] = (ix >= 0 && ix % pi.sx == 0 && ix / pi.sx < pi.nx) ? src[ix / pi.sx] : 0.f;
-    }
-    return make_float2(val[0], val[1]);
-  }, [&](int p, int, float2 u) -> float2 {
-    const PlaneInfo& pi = a.pl[p];
+    const int yy = cell_y(pi);
+    const float* src = a.m + pi.moff + (((size_t)c * pi.nz + pi.k) * pi.ny + (yy < 0 ? 0 : yy)) * pi.nx;
+    const int x0 = cell_x(pi, 2 * mm - pi.ox), x1 = cell_x(pi, 2 * mm + 1 - pi.ox);
+    return make_float2(src[x0 < 0 ? 0 : x0], src[x1 < 0 ? 0 : x1]);
+  }, [&](int p, int mm, float2 u) -> float2 {
+    const PlaneInfo pi = a.pl[p];
     const float sc = a.backward ? 1.0f / pi.vol : (a.ms_mesh ? a.ms_mesh[pi.gid] : a.ms);
-    return make_float2(sc * u.x, sc * u.y);
+    const bool row = cell_y(pi) >= 0;
+    const bool in0 = row && cell_x(pi, 2 * mm - pi.ox) >= 0, in1 = row && cell_x(pi, 2 * mm + 1 - pi.ox) >= 0;
+    return make_float2(in0 ? sc * u.x : 0.f, in1 ? sc * u.y : 0.f);
   });
   const int Kx = a.Kx;
   for (int it = threadIdx.x; it < a.P * Kx; it += FWD_THREADS) {
@@ -68,9 +78,9 @@ __global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_e
   __syncthreads();
   xinv_rows<LNX, INV_THREADS>(smem, tab, a.tw, a.P, PITCH, [&](int p, int mm, float2 uu) {
     const PlaneInfo pi = a.pl[p];
-    const int jy = v - pi.oy;
-    if (jy < 0 || jy % pi.sy != 0 || jy / pi.sy >= pi.ny) return;
-    const size_t row = pi.moff + (((size_t)c * pi.nz + pi.k) * pi.ny + jy / pi.sy) * pi.nx;
+    const int yy = on_stride(v - pi.oy, pi.sy, pi.ny);
+    if (yy < 0) return;
+    const size_t row = pi.moff + (((size_t)c * pi.nz + pi.k) * pi.ny + yy) * pi.nx;
     float post = 1.f, beta = 0.f;
     if (a.backward) {
       post = (a.ms_mesh ? a.ms_mesh[pi.gid] : a.ms) * pi.vol;
@@ -78,9 +88,9 @@ __global__ void __launch_bounds__(INV_THREADS) __attribute__((amdgpu_waves_per_e
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int ix = 2 * mm + h - pi.ox;
-      if (ix >= 0 && ix % pi.sx == 0 && ix / pi.sx < pi.nx) {
-        const size_t o = row + ix / pi.sx;
+      const int xx = on_stride(2 * mm + h - pi.ox, pi.sx, pi.nx);
+      if (xx >= 0) {
+        const size_t o = row + xx;
         float val = h ? uu.y : uu.x;
         if (a.backward) val = post * (val + (a.beta_ptr ? beta * a.aux[o] : 0.f));
         a.H[o] = a.accumulate ? a.H[o] + val : val;
