@@ -257,13 +257,16 @@ k_mid(MidArgs a) {
     return (((size_t)c * a.Nz + kz) * a.Kx + kx) * NY + (size_t)r * M + (t + T * j);
   };
   if constexpr (MODE == 2) {
-    if constexpr (M > R) fill_stage_table<M, R>(tab, a.tw, tid, NTHK);
-    if constexpr (NRES == 2) fill_residue_table<M>(rtab, a.tw, tid, NTHK);
-    __syncthreads();   // tables complete before any transform reads them
+    // tables first, then the spectra (lanes of columns past Kx read S[0]: their
+    // results land only in padding columns), then the tables to LDS
+    TabRegs<M, R, NTHK, NRES == 2> tabs;
+    tabs.load(a.tw, tid);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int j = 0; j < R; ++j) v[c][j] = valid ? a.S[sidx(c, j)] : make_float2(0.f, 0.f);
+      for (int j = 0; j < R; ++j) v[c][j] = a.S[valid ? sidx(c, j) : 0];
+    tabs.store(tab, rtab, tid);
+    __syncthreads();   // tables complete before any transform reads them
   } else {
     // the three components' blocks are loaded at once (16-byte copies, KW/2
     // float4 per y row of the half tile) and staged through LDS together,
