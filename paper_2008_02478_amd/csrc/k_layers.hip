@@ -220,24 +220,34 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 6
 
 // energies of the meshes of a group: out[gid] = scale * sum over the mesh's
 // planes and all workgroups' partials (fixed order)
-__global__ void __launch_bounds__(FINAL_THREADS) k_lenergy(const double* part, int nblk, int P, const PlaneInfo* pl,
+template <int P>
+__global__ void __launch_bounds__(FINAL_THREADS) k_lenergy(const double* part, int nblk, const PlaneInfo* pl,
                                                            double scale, double* out) {
+  static_assert(P >= 1 && P <= MAXP, "planes per group");
   constexpr int NW = FINAL_THREADS / 64;
+  constexpr int U = 4;                      // workgroup entries per thread and sweep
   __shared__ double red[NW][MAXP];
   __shared__ double tot[MAXP];
   __shared__ int gid[MAXP];
-  // every plane's partials of a workgroup entry at once (P contiguous words)
-  double acc[MAXP];
+  // every plane's partials of U workgroup entries at once (P contiguous words
+  // each), all reads issued before any is summed; entries past nblk read
+  // entry 0 and add nothing.  Each plane's sum runs over the entries in
+  // increasing order.
+  double acc[P];
 #pragma unroll
-  for (int p = 0; p < MAXP; ++p) acc[p] = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += FINAL_THREADS) {
-    // unconditional reads (slots past P re-read plane 0), so that all are in
-    // flight at once
-    double v[MAXP];
+  for (int p = 0; p < P; ++p) acc[p] = 0.0;
+  for (int i0 = threadIdx.x; i0 < nblk; i0 += U * FINAL_THREADS) {
+    double v[U][P];
 #pragma unroll
-    for (int p = 0; p < MAXP; ++p) v[p] = part[(size_t)i * P + (p < P ? p : 0)];
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * FINAL_THREADS;
 #pragma unroll
-    for (int p = 0; p < MAXP; ++p) acc[p] += p < P ? v[p] : 0.0;
+      for (int p = 0; p < P; ++p) v[u][p] = part[(size_t)(i < nblk ? i : 0) * P + p];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int p = 0; p < P; ++p) acc[p] += i0 + u * FINAL_THREADS < nblk ? v[u][p] : 0.0;
   }
   if ((int)threadIdx.x < P) gid[threadIdx.x] = pl[threadIdx.x].gid;
   // all planes' wavefront sums together (independent butterflies), then the
@@ -245,12 +255,12 @@ __global__ void __launch_bounds__(FINAL_THREADS) k_lenergy(const double* part, i
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
-    for (int p = 0; p < MAXP; ++p) acc[p] += __shfl_xor(acc[p], o);
+    for (int p = 0; p < P; ++p) acc[p] += __shfl_xor(acc[p], o);
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) {
 #pragma unroll
-    for (int p = 0; p < MAXP; ++p) red[w][p] = acc[p];
+    for (int p = 0; p < P; ++p) red[w][p] = acc[p];
   }
   __syncthreads();
   if ((int)threadIdx.x < P) {
@@ -337,10 +347,26 @@ hipError_t launch_couple(int P, const CoupleArgs& a, hipStream_t s) {
   }
 }
 
+template <int P>
+static hipError_t lenergy_one(const double* part, int nblk, const PlaneInfo* pl, double scale, double* out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL((k_lenergy<P>), dim3(1), dim3(FINAL_THREADS), 0, s, part, nblk, pl, scale, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_layer_energy(const double* part, int nblk, int P, const PlaneInfo* pl, double scale, double* out,
                                hipStream_t s) {
-  hipLaunchKernelGGL(k_lenergy, dim3(1), dim3(FINAL_THREADS), 0, s, part, nblk, P, pl, scale, out);
-  return hipGetLastError();
+  switch (P) {
+    case 1: return lenergy_one<1>(part, nblk, pl, scale, out, s);
+    case 2: return lenergy_one<2>(part, nblk, pl, scale, out, s);
+    case 3: return lenergy_one<3>(part, nblk, pl, scale, out, s);
+    case 4: return lenergy_one<4>(part, nblk, pl, scale, out, s);
+    case 5: return lenergy_one<5>(part, nblk, pl, scale, out, s);
+    case 6: return lenergy_one<6>(part, nblk, pl, scale, out, s);
+    case 7: return lenergy_one<7>(part, nblk, pl, scale, out, s);
+    case 8: return lenergy_one<8>(part, nblk, pl, scale, out, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace demag
