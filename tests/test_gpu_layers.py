@@ -69,6 +69,27 @@ def test_tiny_group_against_direct_sum_with_energy_and_gradient(torch):
     assert errg < TOL
 
 
+def test_group_with_in_plane_offsets_and_stride_four(torch):
+    """Planes on the fine in-plane lattice at offsets of whole fine cells, one
+    layer with cells four times the finest: the embedding and decimation of
+    the layer x passes (cells found on a stride with an offset) against the
+    Eq. 4 direct sum, field and energies."""
+    meshes = [((12, 9, 1), (1e-9, 1e-9, 1e-9)), ((3, 2, 2), (4e-9, 4e-9, 1e-9)), ((5, 4, 1), (1e-9, 1e-9, 1e-9))]
+    orig = [(0.0, 0.0, 0.0), (1e-9, 2e-9, 2e-9), (3e-9, 1e-9, 5e-9)]
+    Ms = [8e5, 1.0e6, 6e5]
+    say("coupled group with in-plane offsets and a stride-4 layer")
+    r = run(torch, meshes, orig, Ms, 60)
+    M = [Ms[i] * r["m"][i].astype(np.float64) for i in range(3)]
+    Hr = ml.field([(n, h, o) for (n, h), o in zip(meshes, orig)], M)
+    err = rel_l2(np.concatenate([x.ravel() for x in r["H"]]), np.concatenate([x.ravel() for x in Hr]))
+    say(f"  field rel-L2 {err:.2e}")
+    assert err < TOL
+    for i, (n, h) in enumerate(meshes):
+        V = h[0] * h[1] * h[2]
+        Er = -0.5 * MU0 * V * float(np.sum(M[i] * Hr[i]))
+        assert abs(r["E"][i] - Er) < TOL * abs(Er) + 1e-3 * TOL * max(abs(x) for x in r["E"]), (i, r["E"][i], Er)
+
+
 def test_split_layers_equal_single_mesh(torch):
     # two single-plane layers stacked at zero gap reproduce one two-plane mesh
     from paper_2008_02478_amd.demag import DemagPlan
