@@ -657,17 +657,19 @@ __global__ void __launch_bounds__(FINAL_THREADS) k_energy_final(const double* pa
   __shared__ double red[FINAL_THREADS / 64];
   const int b = blockIdx.x;
   part += (size_t)b * n;
-  // four independent sums per thread, so that four reads are in flight
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int i = threadIdx.x;
-  for (; i + 3 * FINAL_THREADS < n; i += 4 * FINAL_THREADS) {
-    s0 += part[i];
-    s1 += part[i + FINAL_THREADS];
-    s2 += part[i + 2 * FINAL_THREADS];
-    s3 += part[i + 3 * FINAL_THREADS];
+  // eight partials per thread and sweep, all read before any is added (one
+  // memory round trip up to 8 FINAL_THREADS partials); each thread adds its
+  // partials in increasing order, entries past n read entry 0 and add nothing
+  constexpr int U = 8;
+  double acc = 0.0;
+  for (int i0 = threadIdx.x; i0 < n; i0 += U * FINAL_THREADS) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = part[i0 + u * FINAL_THREADS < n ? i0 + u * FINAL_THREADS : 0];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += i0 + u * FINAL_THREADS < n ? v[u] : 0.0;
   }
-  for (; i < n; i += FINAL_THREADS) s0 += part[i];
-  const double s = block_sum((s0 + s1) + (s2 + s3), red);
+  const double s = block_sum(acc, red);
   if (threadIdx.x == 0) out[gid ? gid[b] : b] = scale * s;
 }
 

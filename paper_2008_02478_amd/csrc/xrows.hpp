@@ -33,8 +33,8 @@ constexpr int xtab_points() {
 // round i is transformed.  load must read in-range memory for every m < L/2
 // (clamping its index, or returning zeros itself) and is called for row <
 // rows only; branch-free loads are issued unconditionally, so the waits for
-// them count exactly.  On return
-// row r of smem holds X[0..L].  Ends with a workgroup barrier.
+// them count exactly.  On return row r of smem holds X[0..L].  Ends with a
+// workgroup barrier.
 template <int LNX, int NTH, typename Load, typename Scale>
 __device__ __forceinline__ void xfwd_rows(float2* __restrict__ smem, float2* __restrict__ tab,
                                           const float2* __restrict__ tw, int rows, int pitch, Load&& load,
